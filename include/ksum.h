@@ -1,0 +1,201 @@
+/*
+ * ksum -- sliced fast kernel summation on AMD MI355X (gfx950).
+ *
+ * Computes s_m = sum_{n=1}^{N} w_n K(x_n, y_m), m = 1..M, for radial kernels
+ * K(x, y) = F(||x - y||) on R^d, by the slicing method of Hertrich, "Fast Kernel
+ * Summation in High Dimensions via Slicing and Fourier Transforms":
+ *
+ *   s_m ~= (1/P) sum_p t_{m,p},  t_{m,p} = sum_n w_n k(<xi_p, x_n>, <xi_p, y_m>)
+ *
+ * (Algorithm "Sliced Fast Fourier Summation", Sec. 3), where k(s,t) = f(|s-t|)
+ * is the one-dimensional counterpart of K (Table "tab:kernels") and xi_p are
+ * random directions on the sphere.  The 1-D sums use
+ *   - fast Fourier summation (Sec. 3.1) with direct transforms (NDFT) or the
+ *     non-equispaced FFT (NFFT) for the Gaussian,
+ *   - sorting + prefix sums (Sec. 3.2, Algorithm "fastsum_energy") for the
+ *     negative distance kernel,
+ *   - both, after splitting K = K1 + K2 (Sec. 3.3), for the Laplacian.
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments named x, y, w, s, grad_* and ws are HIP *device* pointers
+ *     owned by the caller; a plan owns its own device tables.  Host pointers are
+ *     named host_* or are documented as host memory.
+ *   - Points are row-major and contiguous: x is N x d, y is M x d.
+ *   - Calls that take a stream are asynchronous on that stream (a hipStream_t
+ *     passed as void*, NULL = the null stream); argument errors are reported
+ *     synchronously by the return value, device faults surface as KSUM_EDEVICE
+ *     at a later call that synchronises.
+ *   - No entry point aborts or throws; no entry point that takes a workspace
+ *     allocates device memory.  ksum_last_error() describes the last failure of
+ *     the calling thread.
+ *   - A plan is immutable after creation; concurrent ksum_execute calls on one
+ *     plan need distinct workspaces.
+ */
+#ifndef KSUM_H
+#define KSUM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ksum_plan ksum_plan;
+
+/* Kernels (Table "tab:kernels").  sigma is the Gaussian bandwidth,
+ * K = exp(-||x-y||^2 / (2 sigma^2)); the Laplacian is K = exp(-alpha ||x-y||)
+ * with alpha = 1/sigma; the negative distance kernel is K = -||x-y||. */
+typedef enum {
+  KSUM_GAUSSIAN = 1,
+  KSUM_LAPLACIAN = 2,
+  KSUM_NEGDIST = 3
+} ksum_kernel;
+
+/* One-dimensional summation method.  AUTO picks NDFT for the Gaussian with at
+ * most 64 coefficients and NFFT above, NFFT (smooth part) + SORT for the
+ * Laplacian and SORT for the negative distance. */
+typedef enum {
+  KSUM_1D_AUTO = 0,
+  KSUM_1D_NDFT = 1,
+  KSUM_1D_NFFT = 2,
+  KSUM_1D_SORT = 3
+} ksum_method;
+
+/* Arithmetic of the projection GEMM.  FP32 uses FP32 matrix cores. */
+typedef enum {
+  KSUM_FP32 = 0,
+  KSUM_SPLIT_BF16 = 1
+} ksum_precision;
+
+typedef enum {
+  KSUM_OK = 0,
+  KSUM_EINVAL = 1,        /* invalid argument (null pointer, size <= 0, bad parameter) */
+  KSUM_EUNSUPPORTED = 2,  /* valid but not supported (e.g. a method the kernel cannot use) */
+  KSUM_ENOMEM = 3,        /* device or host allocation failed at plan time */
+  KSUM_EWORKSPACE = 4,    /* workspace smaller than ksum_workspace_size() */
+  KSUM_ENONFINITE = 5,    /* reserved: non-finite input detected */
+  KSUM_EDEVICE = 6        /* HIP runtime error, or no usable device */
+} ksum_status;
+
+/* Plan parameters.  Fill with ksum_params_default(), then override fields.
+ *   sigma       kernel scale (> 0; Gaussian bandwidth, Laplacian 1/alpha; unused for NEGDIST)
+ *   seed        seed of the direction generator (see ksum_generate_directions)
+ *   directions  optional host array P*d (FP64, row p = xi_p, unit norm) used instead
+ *               of the generator; copied at plan creation; may be NULL
+ *   n_coeff     Fourier coefficients: NDFT uses k = -n_coeff/2..n_coeff/2, NFFT the
+ *               index set -n_coeff/2..n_coeff/2-1 with the coefficient at -n_coeff/2
+ *               set to 0 (so the sum stays real); even, 2..4096
+ *   coeff_eps   cutoff of eq. "Fourier_cutoff": coefficients with |c_k| <= eps are dropped
+ *   T           rescaling threshold of Sec. 3.1, 0 < T < 0.25 (0 = method default:
+ *               Gaussian NDFT 0.045, Gaussian NFFT 0.02, Laplacian 0.125)
+ *   oversample  NFFT grid oversampling (2 or 4); grid size n = oversample * n_coeff
+ *   window_m    NFFT Kaiser-Bessel window half-width in grid cells (2..8)
+ *   method      ksum_method
+ *   precision   ksum_precision
+ *   slice_batch slices per batch B (0 = all P); bounds the workspace (Remark on
+ *               memory requirements and batching, Sec. 4.4)
+ *   device      HIP device ordinal the plan is created on */
+typedef struct {
+  double sigma;
+  uint64_t seed;
+  const double *directions;
+  int32_t n_coeff;
+  double coeff_eps;
+  double T;
+  int32_t oversample;
+  int32_t window_m;
+  int32_t method;
+  int32_t precision;
+  int32_t slice_batch;
+  int32_t device;
+} ksum_params;
+
+/* Optional intermediate outputs of ksum_execute_probe (each pointer may be NULL).
+ *   z      device float[P][M+N]: projections <xi_p, .>, targets first, then sources
+ *   bounds device double[P][2]: c_min, c_max of each slice (the FP32 values used)
+ *   t      device float[P][M]: the per-slice 1-D sums t_{m,p}
+ *   perm   device int32[P][M+N]: the stable ascending order of each slice's
+ *          projections (union index: 0..M-1 targets, M..M+N-1 sources); only
+ *          produced by methods that sort (NEGDIST, LAPLACIAN) */
+typedef struct {
+  float *z;
+  double *bounds;
+  float *t;
+  int32_t *perm;
+} ksum_probe;
+
+/* Library version string. */
+const char *ksum_version(void);
+
+/* Human-readable name of a status code (static storage). */
+const char *ksum_status_string(ksum_status status);
+
+/* Message describing the last failed call on the calling thread ("" if none). */
+const char *ksum_last_error(void);
+
+/* Default parameters for a kernel (host only, no device access).
+ * EINVAL if out is NULL or kernel is unknown. */
+ksum_status ksum_params_default(ksum_kernel kernel, ksum_params *out);
+
+/* Validate (d, P, kernel, params) exactly as ksum_plan_create does, without
+ * touching a device.  Returns KSUM_OK or the status plan creation would return. */
+ksum_status ksum_check_params(int32_t d, int32_t P, ksum_kernel kernel, const ksum_params *params);
+
+/* Draw P directions uniform on S^{d-1} into host_out (host, FP64, P*d, row-major).
+ * The first step of Algorithm "Sliced Fast Fourier Summation" leaves the
+ * generator open; this one is: SplitMix64 (Steele, Lea, Flood 2014) output number
+ * c of seed s is mix(s + (c+1)*0x9E3779B97F4A7C15); coordinate i of direction p
+ * takes outputs c = 2(p*d+i) and c+1, u1 = ((o1>>11)+1)*2^-53, u2 = (o2>>11)*2^-53,
+ * g = sqrt(-2 ln u1) cos(2 pi u2), and xi_p = g_p/||g_p||.  The first Q directions
+ * do not depend on P.  EINVAL if d < 1, P < 1 or host_out is NULL. */
+ksum_status ksum_generate_directions(int32_t d, int32_t P, uint64_t seed, double *host_out);
+
+/* Workspace bytes an execution with N sources and M targets needs, without a
+ * plan (host only).  EINVAL for invalid parameters or N, M < 1. */
+ksum_status ksum_workspace_bytes(int32_t d, int32_t P, ksum_kernel kernel, const ksum_params *params,
+                                 int64_t N, int64_t M, size_t *bytes);
+
+/* Create a plan for dimension d >= 1 and P >= 1 directions (the problem statement
+ * of Sec. 1 fixes d, the kernel and its parameters; Sec. 2.3 the directions).
+ * params may be NULL (defaults).  Draws the directions, precomputes the window
+ * and coefficient tables and uploads them to params->device.  The plan owns
+ * everything it allocates; release it with ksum_plan_destroy.
+ * EINVAL / EUNSUPPORTED for bad arguments, ENOMEM, EDEVICE without a device. */
+ksum_status ksum_plan_create(int32_t d, int32_t P, ksum_kernel kernel, const ksum_params *params,
+                             ksum_plan **out);
+
+/* Release a plan (NULL is accepted).  Synchronises the plan's device. */
+ksum_status ksum_plan_destroy(ksum_plan *plan);
+
+/* Copy the plan's directions (P*d FP64, row-major) to host_out. */
+ksum_status ksum_get_directions(const ksum_plan *plan, double *host_out);
+
+/* Workspace bytes ksum_execute needs for N sources and M targets. */
+ksum_status ksum_workspace_size(const ksum_plan *plan, int64_t N, int64_t M, size_t *bytes);
+
+/* Forward sliced kernel sum (Algorithm "Sliced Fast Fourier Summation").
+ *   x   device float[N][d] sources          y  device float[M][d] targets
+ *   w   device float[N] weights             s  device float[M] output (overwritten)
+ *   ws  device workspace of ws_bytes >= ksum_workspace_size(plan, N, M)
+ *   stream  hipStream_t (as void*) the work is enqueued on
+ * x and y may alias; s must not overlap any input or the workspace.
+ * EINVAL for null pointers or N, M < 1; EWORKSPACE if ws_bytes is too small. */
+ksum_status ksum_execute(ksum_plan *plan, const float *x, int64_t N, const float *y, int64_t M,
+                         const float *w, float *s, void *ws, size_t ws_bytes, void *stream);
+
+/* As ksum_execute with FP64 inputs x, y, w (converted to FP32 as they are read). */
+ksum_status ksum_execute_f64in(ksum_plan *plan, const double *x, int64_t N, const double *y, int64_t M,
+                               const double *w, float *s, void *ws, size_t ws_bytes, void *stream);
+
+/* As ksum_execute, and also writes the intermediate arrays probe names (probe may
+ * be NULL).  Requesting perm makes ties in the sort ordered by union index. */
+ksum_status ksum_execute_probe(ksum_plan *plan, const float *x, int64_t N, const float *y, int64_t M,
+                               const float *w, float *s, void *ws, size_t ws_bytes, void *stream,
+                               const ksum_probe *probe);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KSUM_H */

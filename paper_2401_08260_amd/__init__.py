@@ -1,0 +1,249 @@
+"""ksum: sliced fast kernel summation on AMD MI355X -- Python binding.
+
+A thin ctypes layer over the C ABI in include/ksum.h (libksum.so, built by
+``paper_2401_08260_amd.build``).  Functions keep the C names and only marshal
+arguments; every step of the computation runs in the HIP library.  ``Plan`` is a
+convenience wrapper that takes torch tensors on the GPU and uses torch's
+current stream.  Importing this module fails loudly if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libksum.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+                      "or `python paper_2401_08260_amd/build.py`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# enums (include/ksum.h)
+KSUM_GAUSSIAN, KSUM_LAPLACIAN, KSUM_NEGDIST = 1, 2, 3
+KSUM_1D_AUTO, KSUM_1D_NDFT, KSUM_1D_NFFT, KSUM_1D_SORT = 0, 1, 2, 3
+KSUM_FP32, KSUM_SPLIT_BF16 = 0, 1
+KSUM_OK, KSUM_EINVAL, KSUM_EUNSUPPORTED, KSUM_ENOMEM, KSUM_EWORKSPACE, KSUM_ENONFINITE, KSUM_EDEVICE = range(7)
+
+KERNELS = {"gaussian": KSUM_GAUSSIAN, "laplacian": KSUM_LAPLACIAN, "negdist": KSUM_NEGDIST}
+METHODS = {"auto": KSUM_1D_AUTO, "ndft": KSUM_1D_NDFT, "nfft": KSUM_1D_NFFT, "sort": KSUM_1D_SORT}
+
+
+class ksum_params(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("directions", ctypes.POINTER(ctypes.c_double)), ("n_coeff", ctypes.c_int32),
+                ("coeff_eps", ctypes.c_double), ("T", ctypes.c_double), ("oversample", ctypes.c_int32),
+                ("window_m", ctypes.c_int32), ("method", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("slice_batch", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class ksum_probe(ctypes.Structure):
+    _fields_ = [("z", ctypes.c_void_p), ("bounds", ctypes.c_void_p), ("t", ctypes.c_void_p),
+                ("perm", ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_sigs = {
+    "ksum_version": (ctypes.c_char_p, []),
+    "ksum_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "ksum_last_error": (ctypes.c_char_p, []),
+    "ksum_params_default": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ksum_params)]),
+    "ksum_check_params": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(ksum_params)]),
+    "ksum_generate_directions": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, _P]),
+    "ksum_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(ksum_params),
+                                            ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
+    "ksum_plan_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(ksum_params),
+                                        ctypes.POINTER(_P)]),
+    "ksum_plan_destroy": (ctypes.c_int, [_P]),
+    "ksum_get_directions": (ctypes.c_int, [_P, _P]),
+    "ksum_workspace_size": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
+    "ksum_execute": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P, ctypes.c_size_t, _P]),
+    "ksum_execute_f64in": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P, ctypes.c_size_t,
+                                          _P]),
+    "ksum_execute_probe": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P, ctypes.c_size_t,
+                                          _P, ctypes.POINTER(ksum_probe)]),
+}
+for _name, (_res, _args) in _sigs.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = tuple(_sigs)
+
+
+class KsumError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.ksum_last_error().decode()
+        super().__init__(f"{where}: {_lib.ksum_status_string(status).decode()} ({msg})")
+
+
+def _check(status: int, where: str) -> None:
+    if status != KSUM_OK:
+        raise KsumError(status, where)
+
+
+# ---------------------------------------------------------------------------
+# C-named wrappers (argument marshalling only)
+# ---------------------------------------------------------------------------
+def ksum_version() -> str:
+    return _lib.ksum_version().decode()
+
+
+def ksum_status_string(status: int) -> str:
+    return _lib.ksum_status_string(status).decode()
+
+
+def ksum_last_error() -> str:
+    return _lib.ksum_last_error().decode()
+
+
+def ksum_params_default(kernel: int) -> ksum_params:
+    p = ksum_params()
+    _check(_lib.ksum_params_default(kernel, ctypes.byref(p)), "ksum_params_default")
+    return p
+
+
+def make_params(kernel: int, directions: Optional[np.ndarray] = None, **overrides) -> ksum_params:
+    """Defaults for `kernel` with fields overridden by keyword (method may be a name)."""
+    p = ksum_params_default(kernel)
+    for k, v in overrides.items():
+        if k == "method" and isinstance(v, str):
+            v = METHODS[v]
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    if directions is not None:
+        arr = np.ascontiguousarray(directions, dtype=np.float64)
+        p._dir_keepalive = arr
+        p.directions = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return p
+
+
+def ksum_check_params(d: int, P: int, kernel: int, params: Optional[ksum_params] = None) -> int:
+    return _lib.ksum_check_params(d, P, kernel, ctypes.byref(params) if params is not None else None)
+
+
+def ksum_generate_directions(d: int, P: int, seed: int) -> np.ndarray:
+    out = np.empty((P, d), dtype=np.float64)
+    _check(_lib.ksum_generate_directions(d, P, seed, out.ctypes.data), "ksum_generate_directions")
+    return out
+
+
+def ksum_workspace_bytes(d: int, P: int, kernel: int, params: Optional[ksum_params], N: int, M: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(_lib.ksum_workspace_bytes(d, P, kernel, ctypes.byref(params) if params is not None else None, N, M,
+                                     ctypes.byref(out)), "ksum_workspace_bytes")
+    return out.value
+
+
+def ksum_plan_create(d: int, P: int, kernel: int, params: Optional[ksum_params] = None) -> int:
+    h = _P()
+    _check(_lib.ksum_plan_create(d, P, kernel, ctypes.byref(params) if params is not None else None,
+                                 ctypes.byref(h)), "ksum_plan_create")
+    return h.value
+
+
+def ksum_plan_destroy(plan: int) -> None:
+    _check(_lib.ksum_plan_destroy(plan), "ksum_plan_destroy")
+
+
+def ksum_get_directions(plan: int, d: int, P: int) -> np.ndarray:
+    out = np.empty((P, d), dtype=np.float64)
+    _check(_lib.ksum_get_directions(plan, out.ctypes.data), "ksum_get_directions")
+    return out
+
+
+def ksum_workspace_size(plan: int, N: int, M: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(_lib.ksum_workspace_size(plan, N, M, ctypes.byref(out)), "ksum_workspace_size")
+    return out.value
+
+
+def ksum_execute(plan: int, x: int, N: int, y: int, M: int, w: int, s: int, ws: int, ws_bytes: int,
+                 stream: int) -> None:
+    _check(_lib.ksum_execute(plan, x, N, y, M, w, s, ws, ws_bytes, stream), "ksum_execute")
+
+
+def ksum_execute_f64in(plan: int, x: int, N: int, y: int, M: int, w: int, s: int, ws: int, ws_bytes: int,
+                       stream: int) -> None:
+    _check(_lib.ksum_execute_f64in(plan, x, N, y, M, w, s, ws, ws_bytes, stream), "ksum_execute_f64in")
+
+
+def ksum_execute_probe(plan: int, x: int, N: int, y: int, M: int, w: int, s: int, ws: int, ws_bytes: int,
+                       stream: int, probe: Optional[ksum_probe]) -> None:
+    _check(_lib.ksum_execute_probe(plan, x, N, y, M, w, s, ws, ws_bytes, stream,
+                                   ctypes.byref(probe) if probe is not None else None), "ksum_execute_probe")
+
+
+# ---------------------------------------------------------------------------
+# torch convenience wrapper
+# ---------------------------------------------------------------------------
+class Plan:
+    """A ksum plan bound to torch device tensors.
+
+    Plan(d, P, "gaussian", sigma=..., seed=..., n_coeff=..., T=..., method="nfft", ...)
+    s = plan(x, y, w)        # x: (N,d), y: (M,d), w: (N,) on the plan's GPU; FP32 or FP64
+    """
+
+    def __init__(self, d: int, P: int, kernel: str, directions: Optional[np.ndarray] = None, **params):
+        import torch  # noqa: F401  (device memory and streams)
+        self.d, self.P = int(d), int(P)
+        self.kernel = kernel
+        self.kid = KERNELS[kernel]
+        self.params = make_params(self.kid, directions=directions, **params)
+        self.handle = ksum_plan_create(self.d, self.P, self.kid, self.params)
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                _lib.ksum_plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def directions(self) -> np.ndarray:
+        return ksum_get_directions(self.handle, self.d, self.P)
+
+    def workspace(self, N: int, M: int, device):
+        import torch
+        need = ksum_workspace_size(self.handle, N, M)
+        if self._ws is None or self._ws.numel() < need or self._ws.device != device:
+            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=device)
+        return self._ws, need
+
+    def __call__(self, x, y, w, out=None, probe: Optional[dict] = None, stream=None):
+        import torch
+        N, M = x.shape[0], y.shape[0]
+        if x.shape[1] != self.d or y.shape[1] != self.d or w.shape[0] != N:
+            raise ValueError("shape mismatch")
+        f64 = x.dtype == torch.float64
+        want = torch.float64 if f64 else torch.float32
+        if y.dtype != want or w.dtype != want:
+            raise TypeError("x, y, w must share one dtype (float32 or float64)")
+        if not (x.is_cuda and y.is_cuda and w.is_cuda):
+            raise ValueError("x, y, w must be GPU tensors")
+        x, y, w = x.contiguous(), y.contiguous(), w.contiguous()
+        s = out if out is not None else torch.empty(M, dtype=torch.float32, device=x.device)
+        ws, need = self.workspace(N, M, x.device)
+        st = (stream if stream is not None else torch.cuda.current_stream(x.device)).cuda_stream
+        if probe is not None:
+            if f64:
+                raise TypeError("probes take FP32 inputs")
+            pr = ksum_probe(*(probe[k].data_ptr() if probe.get(k) is not None else None
+                              for k in ("z", "bounds", "t", "perm")))
+            ksum_execute_probe(self.handle, x.data_ptr(), N, y.data_ptr(), M, w.data_ptr(), s.data_ptr(),
+                               ws.data_ptr(), ws.numel(), st, pr)
+        elif f64:
+            ksum_execute_f64in(self.handle, x.data_ptr(), N, y.data_ptr(), M, w.data_ptr(), s.data_ptr(),
+                               ws.data_ptr(), ws.numel(), st)
+        else:
+            ksum_execute(self.handle, x.data_ptr(), N, y.data_ptr(), M, w.data_ptr(), s.data_ptr(),
+                         ws.data_ptr(), ws.numel(), st)
+        return s

@@ -1,0 +1,154 @@
+// Internal declarations of the ksum library: plan, per-slice parameters,
+// workspace layout and the kernel launch wrappers.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ksum.h"
+
+namespace ksum {
+
+// ---------------------------------------------------------------------------
+// Compile-time limits
+// ---------------------------------------------------------------------------
+constexpr int kMaxTaps = 16;        // 2 * window_m, window_m <= 8
+constexpr int kMaxPolyDeg = 13;     // degree of the per-tap window polynomials
+constexpr int kGemmBK = 16;         // K step of the projection GEMM (d is padded to it)
+constexpr int kGemmBM = 128;        // slices per GEMM tile (P is padded to it)
+constexpr int kSortChunks = 8;      // chunks per slice in the bucket histogram / scatter
+constexpr int kSortCap = 4096;      // elements a bucket group may hold to be sorted in LDS
+constexpr int kSortHalf = kSortCap / 2;
+
+// Kaiser-Bessel window as per-tap polynomials in the fractional grid offset:
+// tap j of a point at grid position u = n x (i0 = floor(u), fr = u - i0) sits on
+// cell i0 - m + 1 + j and has weight phi((fr + m - 1 - j)/n) ~= sum_q c[j][q] (fr - 1/2)^q.
+struct WindowPoly {
+  int32_t taps;                     // 2 m
+  int32_t deg;                      // polynomial degree
+  float c[kMaxTaps][kMaxPolyDeg + 1];
+};
+
+// Per-slice parameters computed on the device from the projection bounds.
+struct SliceParams {
+  double cmin, cmax;      // bounds of the slice's projections (FP32 values as doubles)
+  double cmid;            // (cmin + cmax) / 2
+  double tau;             // 2T / (cmax - cmin)   (Fourier paths)
+  float fcmin;            // cmin as float (bucket map and rescaling)
+  float inv_width;        // buckets per unit length (sort path)
+  float ftau;             // tau as float
+  float shift;            // -T (x~ = tau (x - cmin) - T)
+  int32_t eS;             // fixed-point exponent of sum v (z - cmid)
+  int32_t pad;
+};
+
+struct ksum_plan_impl;  // forward
+
+}  // namespace ksum
+
+// The opaque plan of the C ABI.
+struct ksum_plan {
+  int32_t d = 0, P = 0;
+  ksum_kernel kernel = KSUM_GAUSSIAN;
+  ksum_params params{};          // resolved (no zero "defaults" left), directions pointer cleared
+  int32_t method = 0;            // resolved ksum_method of the smooth part (NDFT/NFFT) or SORT
+  bool use_sort = false;         // a sort pass (NEGDIST, LAPLACIAN)
+  bool use_fourier = false;      // a Fourier pass (GAUSSIAN, LAPLACIAN)
+  int32_t d_pad = 0, P_pad = 0;
+  int32_t K = 0;                 // largest |k| of the symmetric coefficient set
+  int32_t n_grid = 0;            // NFFT grid size
+  double cd = 0;                 // c_d
+  double sort_const = 0;         // constant of the sorted negative-distance part
+  double gauss_logc = 0;         // log(d pi / sqrt(2)) - lgamma((d+2)/2)
+  int32_t lap_L = 0;             // samples of the Laplacian smooth-part recipe
+  std::vector<double> dirs;      // host directions, P x d
+  ksum::WindowPoly poly{};
+  // device tables
+  float *d_dirs = nullptr;       // [P_pad][d_pad] FP32, zero padded
+  float *d_deconv = nullptr;     // [K+1] 1 / (n phihat(k))^2 (NFFT)
+  float2 *d_twiddle = nullptr;   // [n_grid] exp(-2 pi i j / n)
+  double *d_costab = nullptr;    // [lap_L] cos(2 pi j / lap_L)
+};
+
+namespace ksum {
+
+void set_error(const std::string &msg);
+
+// ---------------------------------------------------------------------------
+// Workspace layout for one execution (all offsets 256-byte aligned)
+// ---------------------------------------------------------------------------
+struct Layout {
+  int64_t N = 0, M = 0, L = 0;   // sources, targets, L = M + N
+  int32_t B = 0;                 // slices per batch
+  int32_t nb = 0;                // buckets per slice (sort path)
+  int32_t sort_groups = 0;       // group slots per slice (sort path)
+  int32_t ndft_chunks = 0;       // source chunks per slice (NDFT)
+  int32_t nfft_chunks = 0;       // source chunks per slice (NFFT spread)
+  int32_t win_lo = 0, win_cells = 0;   // NFFT cells touched: [win_lo, win_lo + win_cells)
+  size_t off_misc = 0;           // double[8]: sum|w| and scales
+  size_t off_wpart = 0;          // double[kWsumBlocks]
+  size_t off_params = 0;         // SliceParams[B]
+  size_t off_bounds = 0;         // uint32[B][2]
+  size_t off_z = 0;              // float[B][L]
+  size_t off_t1 = 0;             // float[B][M]
+  size_t off_t2 = 0;             // float[B][M]
+  size_t off_sacc = 0;           // double[M]
+  size_t off_coef = 0;           // float[B][K+1]
+  size_t off_fpart = 0;          // NDFT float2[B][chunks][K+1] or NFFT float[B][chunks][win_cells]
+  size_t off_grid = 0;           // float[B][n_grid]
+  size_t off_lapv = 0;           // double[B][lap_L] samples of the Laplacian recipe
+  size_t off_wf = 0;             // float[N] weights converted from FP64 input
+  size_t off_hcnt = 0;           // uint32[B][kSortChunks][nb]
+  size_t off_hsum = 0;           // int64[B][kSortChunks][nb][2]
+  size_t off_bpre = 0;           // int64[B][nb][2]  exclusive bucket prefix of (A, S)
+  size_t off_boff = 0;           // uint32[B][nb + 1] bucket offsets
+  size_t off_tot = 0;            // int64[B][2]      slice totals (A, S)
+  size_t off_keys = 0;           // uint64[B][L] bucketed (key | index << 32)
+  size_t off_keys2 = 0;          // uint64[B][L] scratch of the large-group sort
+  size_t total = 0;
+};
+
+constexpr int kWsumBlocks = 64;
+
+Layout make_layout(const ksum_plan &plan, int64_t N, int64_t M);
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (defined in the .hip files).  All take the batch's first
+// slice p0 and its size nb_slices; pointers are device pointers.
+// ---------------------------------------------------------------------------
+struct ExecArgs {
+  const ksum_plan *plan;
+  const Layout *lay;
+  char *ws;
+  hipStream_t stream;
+  int32_t p0, nsl;        // batch: slices [p0, p0 + nsl)
+  const void *x, *y;      // FP32 or FP64 points
+  bool f64in;
+  const float *w;         // FP32 weights
+  bool want_perm;         // order ties by union index
+  int32_t *perm_out;      // [P][L] or null
+  float *t_out;           // [P][M] or null (probe)
+};
+
+template <typename T> inline T *wsp(const ExecArgs &a, size_t off) {
+  return reinterpret_cast<T *>(a.ws + off);
+}
+
+hipError_t launch_weight_prep(const ExecArgs &a, const double *w64);
+hipError_t launch_projection(const ExecArgs &a);
+hipError_t launch_slice_setup(const ExecArgs &a);
+hipError_t launch_ndft(const ExecArgs &a);
+hipError_t launch_nfft(const ExecArgs &a);
+hipError_t launch_sort_path(const ExecArgs &a);
+hipError_t launch_accumulate(const ExecArgs &a, float *s, bool first, bool last);
+
+// host tables
+void generate_directions(int32_t d, int32_t P, uint64_t seed, double *out);
+bool build_window_poly(int m, int n, int oversample, WindowPoly *out, std::string *err);
+double kb_phihat(int m, int n, int oversample, int k);
+
+}  // namespace ksum

@@ -1,0 +1,382 @@
+// Fast Fourier summation of Sec. 3.1 on every slice, after the rescaling
+// x~ = tau (x - c_min) - T (Sec. 3.1, "Rescaling"):
+//
+//   w^_k = sum_n w_n exp(-2 pi i k x~_n)           (adjoint transform)
+//   t_m  = sum_k c_k w^_k exp(+2 pi i k y~_m)      (transform at the targets)
+//
+// with real even coefficients c_k (so t_m = c_0 w^_0 + 2 Re sum_{k>=1} ...).
+//
+// NDFT: the transforms evaluated directly, O((N+M)|C|) (Sec. 3.1).
+// NFFT (the Remark "Non-equispaced FFT" of Sec. 3.1): sources are spread onto an
+// oversampled grid of n = sigma_os * n_coeff cells with a Kaiser-Bessel window
+// of half-width m, the grid is transformed by an FFT, multiplied by
+// c_k / (n phi^(k))^2 (deconvolution of both window passes), transformed back,
+// and interpolated at the targets with the same window.  Points only occupy
+// [-T, T], so spreading and interpolation touch a window of W cells around 0;
+// each lane accumulates into its own copy of that window in LDS ([cell][lane]
+// layout: conflict-free, deterministic), then lanes and chunks are reduced in a
+// fixed order.
+#include "device_common.h"
+#include "internal.h"
+
+namespace ksum {
+
+// ---------------------------------------------------------------------------
+// NDFT
+// ---------------------------------------------------------------------------
+constexpr int kNdftChunk = 4096;   // sources per adjoint block
+constexpr int kNdftKB = 32;        // coefficients per register block
+
+struct FourierArgs {
+  int32_t nsl, K, chunks;
+  int64_t N, M, L;
+  const float *Z;
+  const float *w;
+  const SliceParams *params;
+  const float *coef;       // [nsl][K+1]
+  float2 *part;            // NDFT: [nsl][chunks][K+1]
+  float *gpart;            // NFFT: [nsl][chunks][W]
+  float *gwin;             // NFFT: [nsl][W] interpolation grid window
+  float *t;                // [nsl][M]
+  // NFFT
+  int32_t n, W, lo;        // grid size, window cells, first window cell (may be < 0)
+  int32_t lanes;           // lanes per spread block
+  int32_t i0min, i0max;    // clamp of the base cell
+  const float2 *twiddle;   // [n]
+  WindowPoly poly;
+};
+
+__global__ __launch_bounds__(256) void ndft_adjoint_kernel(FourierArgs a) {
+  __shared__ float2 red[4][kNdftKB];
+  const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * a.chunks);
+  if (work < 0) return;
+  const int p = (int)(work / a.chunks), c = (int)(work % a.chunks);
+  const SliceParams sp = a.params[p];
+  const float *Zx = a.Z + (int64_t)p * a.L + a.M;
+  const int64_t n0 = (int64_t)c * kNdftChunk, n1 = min(a.N, n0 + kNdftChunk);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int kb = 0; kb <= a.K; kb += kNdftKB) {
+    float re[kNdftKB], im[kNdftKB];
+#pragma unroll
+    for (int q = 0; q < kNdftKB; ++q) re[q] = im[q] = 0.f;
+    for (int64_t i = n0 + threadIdx.x; i < n1; i += 256) {
+      const float xt = (Zx[i] - sp.fcmin) * sp.ftau + sp.shift;
+      const float wv = a.w[i];
+#pragma unroll
+      for (int q = 0; q < kNdftKB; ++q) {
+        const int k = kb + q;
+        float s, co;
+        sincospif(2.0f * (float)k * xt, &s, &co);   // exp(-2 pi i k x) = cos - i sin
+        re[q] += wv * co;
+        im[q] -= wv * s;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kNdftKB; ++q) {
+      const float r = wave_sum(re[q]), m = wave_sum(im[q]);
+      if (lane == 0) red[wid][q] = make_float2(r, m);
+    }
+    __syncthreads();
+    if (threadIdx.x < kNdftKB && kb + (int)threadIdx.x <= a.K) {
+      const int q = threadIdx.x;
+      float2 s = red[0][q];
+      for (int w2 = 1; w2 < 4; ++w2) {
+        s.x += red[w2][q].x;
+        s.y += red[w2][q].y;
+      }
+      a.part[((int64_t)p * a.chunks + c) * (a.K + 1) + kb + q] = s;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void ndft_forward_kernel(FourierArgs a, int ychunk) {
+  extern __shared__ float2 h[];   // [K+1]
+  const int nyc = (int)((a.M + ychunk - 1) / ychunk);
+  const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * nyc);
+  if (work < 0) return;
+  const int p = (int)(work / nyc), c = (int)(work % nyc);
+  const SliceParams sp = a.params[p];
+  for (int k = threadIdx.x; k <= a.K; k += blockDim.x) {
+    float2 s = make_float2(0.f, 0.f);
+    const float2 *pp = a.part + (int64_t)p * a.chunks * (a.K + 1) + k;
+    for (int q = 0; q < a.chunks; ++q) {
+      const float2 v = pp[(int64_t)q * (a.K + 1)];
+      s.x += v.x;
+      s.y += v.y;
+    }
+    const float ck = a.coef[(int64_t)p * (a.K + 1) + k];
+    const float f = (k == 0) ? ck : 2.0f * ck;   // c_{-k} w^_{-k} is the conjugate term
+    h[k] = make_float2(f * s.x, f * s.y);
+  }
+  __syncthreads();
+  const float *Zy = a.Z + (int64_t)p * a.L;
+  float *tp = a.t + (int64_t)p * a.M;
+  const int64_t m0 = (int64_t)c * ychunk, m1 = min(a.M, m0 + ychunk);
+  for (int64_t m = m0 + threadIdx.x; m < m1; m += blockDim.x) {
+    const float yt = (Zy[m] - sp.fcmin) * sp.ftau + sp.shift;
+    float acc = 0.f;
+    for (int k = 0; k <= a.K; ++k) {
+      float s, co;
+      sincospif(2.0f * (float)k * yt, &s, &co);
+      // Re((hr + i hi)(cos + i sin)) = hr cos - hi sin
+      acc += h[k].x * co - h[k].y * s;
+    }
+    tp[m] = acc;
+  }
+}
+
+hipError_t launch_ndft(const ExecArgs &a) {
+  const ksum_plan &pl = *a.plan;
+  const Layout &lay = *a.lay;
+  FourierArgs f{};
+  f.nsl = a.nsl;
+  f.K = pl.K;
+  f.chunks = lay.ndft_chunks;
+  f.N = lay.N;
+  f.M = lay.M;
+  f.L = lay.L;
+  f.Z = wsp<float>(a, lay.off_z);
+  f.w = a.w;
+  f.params = wsp<SliceParams>(a, lay.off_params);
+  f.coef = wsp<float>(a, lay.off_coef);
+  f.part = wsp<float2>(a, lay.off_fpart);
+  f.t = wsp<float>(a, lay.off_t1);
+  ndft_adjoint_kernel<<<(unsigned)xcd_grid((int64_t)a.nsl * f.chunks), 256, 0, a.stream>>>(f);
+  const int ychunk = 2048;
+  const int nyc = (int)((lay.M + ychunk - 1) / ychunk);
+  ndft_forward_kernel<<<(unsigned)xcd_grid((int64_t)a.nsl * nyc), 256, (pl.K + 1) * sizeof(float2),
+                        a.stream>>>(f, ychunk);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// NFFT
+// ---------------------------------------------------------------------------
+constexpr int kNfftPPL = 16;   // sources per lane in a spread block
+
+// Window weights of the 2 MW taps of a point with fractional offset x = fr - 1/2:
+// tap j and tap 2 MW - 1 - j are mirror images, poly_{2MW-1-j}(x) = poly_j(-x), so the
+// even and odd parts of the first MW polynomials give all taps.
+template <int MW, int DEG>
+__device__ __forceinline__ void window_taps(const WindowPoly &wp, float x, float (&tap)[2 * MW]) {
+  const float x2 = x * x;
+#pragma unroll
+  for (int j = 0; j < MW; ++j) {
+    float e = wp.c[j][DEG - (DEG & 1)];
+#pragma unroll
+    for (int q = DEG - (DEG & 1) - 2; q >= 0; q -= 2) e = fmaf(e, x2, wp.c[j][q]);
+    float o = wp.c[j][DEG - 1 + (DEG & 1)];
+#pragma unroll
+    for (int q = DEG - 1 + (DEG & 1) - 2; q >= 1; q -= 2) o = fmaf(o, x2, wp.c[j][q]);
+    const float xo = x * o;
+    tap[j] = e + xo;
+    tap[2 * MW - 1 - j] = e - xo;
+  }
+}
+
+template <int MW, int DEG>
+__global__ __launch_bounds__(256) void nfft_spread_kernel(FourierArgs a) {
+  extern __shared__ float acc[];   // [W][lanes]
+  const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * a.chunks);
+  if (work < 0) return;
+  const int p = (int)(work / a.chunks), c = (int)(work % a.chunks);
+  const int lanes = a.lanes;
+  const int t = threadIdx.x;
+  for (int i = t; i < a.W * lanes; i += lanes) acc[i] = 0.f;
+  __syncthreads();
+  const SliceParams sp = a.params[p];
+  const float *Zx = a.Z + (int64_t)p * a.L + a.M;
+  const int64_t chunk = (int64_t)lanes * kNfftPPL;
+  const int64_t n0 = (int64_t)c * chunk, n1 = min(a.N, n0 + chunk);
+  const float fn = (float)a.n;
+  for (int64_t i = n0 + t; i < n1; i += lanes) {
+    const float xt = (Zx[i] - sp.fcmin) * sp.ftau + sp.shift;
+    const float u = xt * fn;
+    int i0 = (int)floorf(u);
+    const float fr = u - (float)i0;
+    i0 = min(max(i0, a.i0min), a.i0max);
+    float tap[2 * MW];
+    window_taps<MW, DEG>(a.poly, fr - 0.5f, tap);
+    const float wv = a.w[i];
+    float *base = acc + (i0 - MW + 1 - a.lo) * lanes + t;
+#pragma unroll
+    for (int j = 0; j < 2 * MW; ++j) base[j * lanes] += wv * tap[j];
+  }
+  __syncthreads();
+  // reduce the lanes of every cell in a fixed order: one wave per cell
+  const int lane = t & 63, wid = t >> 6, nw = lanes >> 6;
+  float *out = a.gpart + ((int64_t)p * a.chunks + c) * a.W;
+  for (int cell = wid; cell < a.W; cell += nw) {
+    float s = 0.f;
+    for (int l = lane; l < lanes; l += 64) s += acc[cell * lanes + l];
+    s = wave_sum(s);
+    if (lane == 0) out[cell] = s;
+  }
+}
+
+// One slice per block: reduce chunk partials, FFT, diagonal, inverse FFT.
+__global__ __launch_bounds__(256) void nfft_grid_kernel(FourierArgs a) {
+  extern __shared__ float2 fbuf[];   // [2][n]
+  const int p = blockIdx.x;
+  const int n = a.n, t = threadIdx.x, lane = t & 63, wid = t >> 6, nw = blockDim.x >> 6;
+  float2 *x = fbuf, *y = fbuf + n;
+  for (int i = t; i < n; i += blockDim.x) x[i] = make_float2(0.f, 0.f);
+  __syncthreads();
+  const float *gp = a.gpart + (int64_t)p * a.chunks * a.W;
+  for (int cell = wid; cell < a.W; cell += nw) {
+    float s = 0.f;
+    for (int q = lane; q < a.chunks; q += 64) s += gp[(int64_t)q * a.W + cell];
+    s = wave_sum(s);
+    if (lane == 0) {
+      int gi = (a.lo + cell) % n;
+      if (gi < 0) gi += n;
+      x[gi].x = s;
+    }
+  }
+  __syncthreads();
+  // forward FFT (radix-2 Stockham): g^_k = sum_l g_l exp(-2 pi i k l / n)
+  for (int Ls = 1; Ls < n; Ls <<= 1) {
+    const int tstep = n / (2 * Ls);
+    for (int j = t; j < n / 2; j += blockDim.x) {
+      const int k = j & (Ls - 1);
+      const float2 A = x[j], Bv = x[j + n / 2];
+      const float2 wv = a.twiddle[k * tstep];
+      const float2 b = make_float2(Bv.x * wv.x - Bv.y * wv.y, Bv.x * wv.y + Bv.y * wv.x);
+      const int o = 2 * j - k;
+      y[o] = make_float2(A.x + b.x, A.y + b.y);
+      y[o + Ls] = make_float2(A.x - b.x, A.y - b.y);
+    }
+    __syncthreads();
+    float2 *tmp = x; x = y; y = tmp;
+  }
+  // diagonal: c_k / (n phi^(k))^2 for |k| <= K, zero elsewhere
+  const float *cf = a.coef + (int64_t)p * (a.K + 1);
+  for (int j = t; j < n; j += blockDim.x) {
+    const int k = (j < n / 2) ? j : j - n;
+    const int ak = k < 0 ? -k : k;
+    const float f = (ak <= a.K) ? cf[ak] : 0.f;
+    x[j] = make_float2(x[j].x * f, x[j].y * f);
+  }
+  __syncthreads();
+  // inverse FFT: G_l = sum_k h_k exp(+2 pi i k l / n)
+  for (int Ls = 1; Ls < n; Ls <<= 1) {
+    const int tstep = n / (2 * Ls);
+    for (int j = t; j < n / 2; j += blockDim.x) {
+      const int k = j & (Ls - 1);
+      const float2 A = x[j], Bv = x[j + n / 2];
+      const float2 wv = a.twiddle[k * tstep];   // conjugated below
+      const float2 b = make_float2(Bv.x * wv.x + Bv.y * wv.y, Bv.y * wv.x - Bv.x * wv.y);
+      const int o = 2 * j - k;
+      y[o] = make_float2(A.x + b.x, A.y + b.y);
+      y[o + Ls] = make_float2(A.x - b.x, A.y - b.y);
+    }
+    __syncthreads();
+    float2 *tmp = x; x = y; y = tmp;
+  }
+  float *gw = a.gwin + (int64_t)p * a.W;
+  for (int cell = t; cell < a.W; cell += blockDim.x) {
+    int gi = (a.lo + cell) % n;
+    if (gi < 0) gi += n;
+    gw[cell] = x[gi].x;
+  }
+}
+
+template <int MW, int DEG>
+__global__ __launch_bounds__(256) void nfft_interp_kernel(FourierArgs a, int ychunk) {
+  extern __shared__ float G[];   // [W]
+  const int nyc = (int)((a.M + ychunk - 1) / ychunk);
+  const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * nyc);
+  if (work < 0) return;
+  const int p = (int)(work / nyc), c = (int)(work % nyc);
+  for (int i = threadIdx.x; i < a.W; i += blockDim.x) G[i] = a.gwin[(int64_t)p * a.W + i];
+  __syncthreads();
+  const SliceParams sp = a.params[p];
+  const float *Zy = a.Z + (int64_t)p * a.L;
+  float *tp = a.t + (int64_t)p * a.M;
+  const float fn = (float)a.n;
+  const int64_t m0 = (int64_t)c * ychunk, m1 = min(a.M, m0 + ychunk);
+  for (int64_t m = m0 + threadIdx.x; m < m1; m += blockDim.x) {
+    const float yt = (Zy[m] - sp.fcmin) * sp.ftau + sp.shift;
+    const float u = yt * fn;
+    int i0 = (int)floorf(u);
+    const float fr = u - (float)i0;
+    i0 = min(max(i0, a.i0min), a.i0max);
+    float tap[2 * MW];
+    window_taps<MW, DEG>(a.poly, fr - 0.5f, tap);
+    const float *gb = G + (i0 - MW + 1 - a.lo);
+    float acc = 0.f;
+#pragma unroll
+    for (int j = 0; j < 2 * MW; ++j) acc = fmaf(gb[j], tap[j], acc);
+    tp[m] = acc;
+  }
+}
+
+template <int MW, int DEG>
+static void launch_nfft_m(const FourierArgs &f, const ExecArgs &a) {
+  const unsigned gs = (unsigned)xcd_grid((int64_t)a.nsl * f.chunks);
+  const size_t spread_lds = (size_t)f.W * f.lanes * sizeof(float);
+  const size_t grid_lds = 2 * (size_t)f.n * sizeof(float2);
+  if (spread_lds > 65536)
+    (void)hipFuncSetAttribute((const void *)nfft_spread_kernel<MW, DEG>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)spread_lds);
+  if (grid_lds > 65536)
+    (void)hipFuncSetAttribute((const void *)nfft_grid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)grid_lds);
+  nfft_spread_kernel<MW, DEG><<<gs, f.lanes, spread_lds, a.stream>>>(f);
+  nfft_grid_kernel<<<a.nsl, 256, grid_lds, a.stream>>>(f);
+  const int ychunk = 4096;
+  const int nyc = (int)((f.M + ychunk - 1) / ychunk);
+  nfft_interp_kernel<MW, DEG><<<(unsigned)xcd_grid((int64_t)a.nsl * nyc), 256, (size_t)f.W * sizeof(float),
+                                a.stream>>>(f, ychunk);
+}
+
+int nfft_lanes_for(int W) {
+  // lanes per spread block: as many as fit 64 KB of per-lane windows (>= 64)
+  int lanes = 256;
+  while (lanes > 64 && (size_t)W * lanes * sizeof(float) > 64 * 1024) lanes >>= 1;
+  return lanes;
+}
+
+hipError_t launch_nfft(const ExecArgs &a) {
+  const ksum_plan &pl = *a.plan;
+  const Layout &lay = *a.lay;
+  FourierArgs f{};
+  f.nsl = a.nsl;
+  f.K = pl.K;
+  f.chunks = lay.nfft_chunks;
+  f.N = lay.N;
+  f.M = lay.M;
+  f.L = lay.L;
+  f.Z = wsp<float>(a, lay.off_z);
+  f.w = a.w;
+  f.params = wsp<SliceParams>(a, lay.off_params);
+  f.coef = wsp<float>(a, lay.off_coef);
+  f.gpart = wsp<float>(a, lay.off_fpart);
+  f.gwin = wsp<float>(a, lay.off_grid);
+  f.t = wsp<float>(a, lay.off_t1);
+  f.n = pl.n_grid;
+  f.W = lay.win_cells;
+  f.lo = lay.win_lo;
+  f.lanes = nfft_lanes_for(lay.win_cells);
+  const int m = pl.params.window_m;
+  f.i0min = lay.win_lo + m - 1;
+  f.i0max = lay.win_lo + lay.win_cells - 1 - m;
+  f.twiddle = pl.d_twiddle;
+  f.poly = pl.poly;
+  switch (m) {
+    case 2: launch_nfft_m<2, 10>(f, a); break;
+    case 3: launch_nfft_m<3, 10>(f, a); break;
+    case 4: launch_nfft_m<4, 10>(f, a); break;
+    case 5: launch_nfft_m<5, 10>(f, a); break;
+    case 6: launch_nfft_m<6, 10>(f, a); break;
+    case 7: launch_nfft_m<7, 12>(f, a); break;
+    case 8: launch_nfft_m<8, 12>(f, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int window_degree_for(int m) { return m <= 6 ? 10 : 12; }
+
+}  // namespace ksum

@@ -1,0 +1,185 @@
+// Per-slice set-up on the device (no host round trip between the projection
+// and the 1-D summations):
+//   * rescaling of Sec. 3.1: c_min, c_max of the slice, tau = 2T/(c_max - c_min),
+//     x~ = tau (x - c_min) - T; a slice whose points all coincide uses
+//     c_max - c_min := sigma (any width is valid there);
+//   * Gaussian Fourier coefficients c_k = f^_{tau sigma}(k) (Lemma
+//     "lem:Fourier_Gauss", evaluated in log space as Sec. 2.2 suggests);
+//   * Laplacian smooth-part coefficients (Sec. 3.3): k1(u) = f(|u|/tau) + alpha c_d |u|/tau
+//     with its linear term removed, multiplied by the taper
+//     W(u) = erfc((|u| - 3/8) * 37) / 2 and integrated over the torus by the
+//     trapezoidal rule on L points;
+//   * the bucket map and fixed-point exponents of the sort path.
+// All coefficient arithmetic is FP64.
+#include "device_common.h"
+#include "internal.h"
+
+namespace ksum {
+
+struct SetupArgs {
+  int32_t nsl;
+  int32_t kernel;
+  int32_t d;
+  int32_t K;              // coefficients for k = 0..K
+  int32_t nfft;           // 1: fold the NFFT deconvolution into the table
+  int32_t nb;             // buckets (sort path)
+  int32_t lap_L;
+  double T, sigma, eps, gauss_logc, cd;
+  const uint32_t *bounds;
+  const double *misc;     // misc[0] = sum |w|
+  const float *deconv;    // [K+1]
+  const double *costab;   // [lap_L]
+  SliceParams *params;
+  float *coef;            // [nsl][K+1]
+  double *lapv;           // [nsl][lap_L]
+  double *bounds_out;     // probe: [P][2] (already offset by p0) or null
+};
+
+// Even part (n = 0, 2, 4, ...) and odd part from n = 3 of the series of the
+// Laplacian counterpart f(t) = sum_n (-a)^n sqrt(pi) Gamma((n+d)/2) / (n! Gamma(d/2) Gamma((n+1)/2)),
+// a = alpha t (Table "tab:kernels").  Both chains follow
+// T_{n+2} = T_n a^2 (n+d) / ((n+1)^2 (n+2)), T_0 = 1, T_1 = -a c_d.
+__device__ double laplace_k1_series(double a, int d, double cd) {
+  const double a2 = a * a;
+  double te = 1.0, to = -a * cd;
+  double even = 1.0, odd3 = 0.0, big = 1.0;
+  for (int n = 0; n < 20000; n += 2) {
+    te *= a2 * (double)(n + d) / ((double)(n + 1) * (double)(n + 1) * (double)(n + 2));
+    to *= a2 * (double)(n + 1 + d) / ((double)(n + 2) * (double)(n + 2) * (double)(n + 3));
+    even += te;
+    odd3 += to;
+    big = fmax(big, fmax(fabs(te), fabs(to)));
+    if (n > 8 && fabs(te) + fabs(to) <= 1e-18 * big) break;
+  }
+  return even + odd3;
+}
+
+__global__ __launch_bounds__(256) void slice_setup_kernel(SetupArgs a) {
+  const int p = blockIdx.x;
+  __shared__ SliceParams sp;
+  if (threadIdx.x == 0) {
+    const float fmin = key_float(a.bounds[2 * p]);
+    const float fmax = key_float(a.bounds[2 * p + 1]);
+    SliceParams q;
+    q.cmin = (double)fmin;
+    q.cmax = (double)fmax;
+    q.cmid = 0.5 * (q.cmin + q.cmax);
+    double range = q.cmax - q.cmin;
+    const bool degenerate = !(range > 0.0);
+    q.fcmin = fmin;
+    q.inv_width = degenerate ? 0.f : (float)((double)a.nb / range);
+    if (degenerate) range = a.sigma;
+    q.tau = 2.0 * a.T / range;
+    q.ftau = (float)q.tau;
+    q.shift = (float)(-a.T);
+    // fixed-point exponent of sum v (z - cmid): 2^eS * sum|w| * max|z - cmid| < 2^61
+    const double wsum = a.misc[0];
+    const double half = 0.5 * (q.cmax - q.cmin) * (1.0 + 1e-12) + 1e-300;
+    int e = 0;
+    if (wsum > 0.0) frexp(wsum * half, &e);
+    q.eS = 61 - e;
+    q.pad = 0;
+    a.params[p] = q;
+    sp = q;
+    if (a.bounds_out) {
+      a.bounds_out[2 * p] = q.cmin;
+      a.bounds_out[2 * p + 1] = q.cmax;
+    }
+  }
+  __syncthreads();
+  if (a.K < 0) return;
+  float *coef = a.coef + (int64_t)p * (a.K + 1);
+  if (a.kernel == KSUM_GAUSSIAN) {
+    const double st = sp.tau * a.sigma;     // f_sigma(u / tau) = f_{tau sigma}(u)
+    for (int k = threadIdx.x; k <= a.K; k += blockDim.x) {
+      double c;
+      if (k == 0) {
+        c = (a.d == 1) ? 2.5066282746310002 * st : 0.0;   // sqrt(2 pi) tau sigma
+      } else {
+        const double z = 19.739208802178716 * st * st * (double)k * (double)k;   // 2 pi^2 s^2 k^2
+        c = exp(a.gauss_logc + log(st) - z + 0.5 * (double)(a.d - 1) * log(z));
+      }
+      if (fabs(c) <= a.eps) c = 0.0;
+      if (a.nfft) c *= (double)a.deconv[k];
+      coef[k] = (float)c;
+    }
+    return;
+  }
+  if (a.kernel == KSUM_LAPLACIAN) {
+    const double alpha_t = 1.0 / (a.sigma * sp.tau);   // alpha / tau
+    const int L = a.lap_L;
+    double *v = a.lapv + (int64_t)p * L;
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+      const double u = -0.5 + (double)j / (double)L;
+      const double au = fabs(u);
+      const double taper = 0.5 * erfc((au - 0.375) * 37.0);
+      v[j] = laplace_k1_series(alpha_t * au, a.d, a.cd) * taper;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k <= a.K; k += blockDim.x) {
+      // c_k = (1/L) sum_j v_j cos(2 pi k u_j),  cos(2 pi k (-1/2 + j/L)) = (-1)^k cos(2 pi k j / L)
+      double acc = 0.0;
+      int idx = 0;
+      for (int j = 0; j < L; ++j) {
+        acc += v[j] * a.costab[idx];
+        idx += k;
+        if (idx >= L) idx -= L;
+      }
+      double c = acc / (double)L;
+      if (k & 1) c = -c;
+      if (fabs(c) <= a.eps) c = 0.0;
+      if (a.nfft) c *= (double)a.deconv[k];
+      coef[k] = (float)c;
+    }
+  }
+}
+
+hipError_t launch_slice_setup(const ExecArgs &a) {
+  const ksum_plan &pl = *a.plan;
+  const Layout &lay = *a.lay;
+  SetupArgs s{};
+  s.nsl = a.nsl;
+  s.kernel = pl.kernel;
+  s.d = pl.d;
+  s.K = pl.use_fourier ? pl.K : -1;
+  s.nfft = (pl.method == KSUM_1D_NFFT) ? 1 : 0;
+  s.nb = lay.nb;
+  s.lap_L = pl.lap_L;
+  s.T = pl.params.T;
+  s.sigma = pl.params.sigma;
+  s.eps = pl.params.coeff_eps;
+  s.gauss_logc = pl.gauss_logc;
+  s.cd = pl.cd;
+  s.bounds = wsp<uint32_t>(a, lay.off_bounds);
+  s.misc = wsp<double>(a, lay.off_misc);
+  s.deconv = pl.d_deconv;
+  s.costab = pl.d_costab;
+  s.params = wsp<SliceParams>(a, lay.off_params);
+  s.coef = wsp<float>(a, lay.off_coef);
+  s.lapv = wsp<double>(a, lay.off_lapv);
+  s.bounds_out = nullptr;
+  slice_setup_kernel<<<a.nsl, 256, 0, a.stream>>>(s);
+  return hipGetLastError();
+}
+
+hipError_t launch_bounds_probe(const ExecArgs &a, double *bounds_out) {
+  // re-run the (cheap) parameter part to export the bounds of this batch
+  const ksum_plan &pl = *a.plan;
+  const Layout &lay = *a.lay;
+  SetupArgs s{};
+  s.nsl = a.nsl;
+  s.kernel = pl.kernel;
+  s.d = pl.d;
+  s.K = -1;
+  s.nb = lay.nb;
+  s.T = pl.params.T;
+  s.sigma = pl.params.sigma;
+  s.bounds = wsp<uint32_t>(a, lay.off_bounds);
+  s.misc = wsp<double>(a, lay.off_misc);
+  s.params = wsp<SliceParams>(a, lay.off_params);
+  s.bounds_out = bounds_out + 2 * (int64_t)a.p0;
+  slice_setup_kernel<<<a.nsl, 64, 0, a.stream>>>(s);
+  return hipGetLastError();
+}
+
+}  // namespace ksum

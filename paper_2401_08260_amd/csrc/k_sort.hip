@@ -1,0 +1,586 @@
+// Sort path of the negative distance kernel (Sec. 3.2) and of the K2 part of
+// the Laplacian (Sec. 3.3): for every slice,
+//
+//   t_m = -c' sum_n v_n |z_n - z_m|   over the union z = (y, x), v = (0, w),
+//
+// evaluated at the targets through the sorted order.  With A_<(m) and S_<(m)
+// the sums of v and v z over the entries sorted before target m,
+//
+//   t_m = -c' [ z_m (2 A_< - A_tot) - (2 S_< - S_tot) ],
+//
+// which is Algorithm "fastsum_energy" regrouped (b_{m-1} and a_L (z_L - z_m)
+// expanded into A and S); ties contribute 0 in either form.
+//
+// Implementation (per slice, all slices of a batch at once):
+//   S1 hist     linear-in-value buckets over [c_min, c_max] (a monotone map, so
+//               bucket order is value order); per bucket the count and the sums
+//               of v and v (z - c_mid) as 64-bit fixed-point integers, so every
+//               sum is exact and independent of the order of the atomics
+//   S2 scan     bucket offsets and exclusive bucket prefixes of (A, S)
+//   S3 scatter  (key, union index) pairs into their buckets
+//   S4 groups   consecutive buckets holding about 2048..4096 entries are sorted
+//               in LDS (stable LSD radix on 8-bit digits, wave ballots for the
+//               in-wave ranks), ties ordered by union index, then a block scan
+//               of the fixed-point (A, S) gives t at every target.  A group
+//               larger than LDS is sorted by one workgroup streaming through
+//               global memory with the same ranking.
+// The order produced is the stable ascending order of the FP32 projections
+// (ties by union index), i.e. the permutation sigma of Sec. 3.2.
+#include "device_common.h"
+#include "internal.h"
+
+namespace ksum {
+
+struct SortArgs {
+  int32_t nsl, nb, G;
+  int64_t L, M;
+  const float *Z;
+  const float *w;
+  const SliceParams *params;
+  const double *misc;
+  uint32_t *hcnt;
+  long long *hsum;
+  long long *bpre;
+  uint32_t *boff;
+  long long *tot;
+  unsigned long long *keys;
+  unsigned long long *keys2;
+  float *t;             // [nsl][M]
+  int32_t *perm;        // [nsl][L] (already offset to the batch) or null
+  double cneg;          // c' (c_d, or alpha c_d for the Laplacian)
+};
+
+__device__ __forceinline__ int bucket_of(float z, float fcmin, float invw, int nb) {
+  const float q = (z - fcmin) * invw;
+  return (q < (float)nb) ? (int)q : nb - 1;     // q >= 0; inf / NaN go to the last bucket
+}
+
+__device__ __forceinline__ long long fix_a(float v, int eA) {
+  return __double2ll_rn(ldexp((double)v, eA));
+}
+
+__device__ __forceinline__ long long fix_s(float v, float z, double cmid, int eS) {
+  return __double2ll_rn(ldexp((double)v * ((double)z - cmid), eS));
+}
+
+// ---------------------------------------------------------------------------
+// S1: per (slice, chunk) bucket histogram with fixed-point sums
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(512) void sort_hist_kernel(SortArgs a) {
+  __shared__ uint32_t cnt[2048];
+  __shared__ unsigned long long sA[2048], sS[2048];
+  const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * kSortChunks);
+  if (work < 0) return;
+  const int p = (int)(work / kSortChunks), c = (int)(work % kSortChunks);
+  for (int b = threadIdx.x; b < a.nb; b += blockDim.x) {
+    cnt[b] = 0;
+    sA[b] = 0;
+    sS[b] = 0;
+  }
+  __syncthreads();
+  const SliceParams sp = a.params[p];
+  const int eA = (int)a.misc[1];
+  const int64_t chunk = (a.L + kSortChunks - 1) / kSortChunks;
+  const int64_t l0 = c * chunk, l1 = min(a.L, l0 + chunk);
+  const float *Zp = a.Z + (int64_t)p * a.L;
+  for (int64_t l = l0 + threadIdx.x; l < l1; l += blockDim.x) {
+    const float z = Zp[l];
+    const int b = bucket_of(z, sp.fcmin, sp.inv_width, a.nb);
+    atomicAdd(&cnt[b], 1u);
+    if (l >= a.M) {
+      const float v = a.w[l - a.M];
+      atomicAdd(&sA[b], (unsigned long long)fix_a(v, eA));
+      atomicAdd(&sS[b], (unsigned long long)fix_s(v, z, sp.cmid, sp.eS));
+    }
+  }
+  __syncthreads();
+  const int64_t base = ((int64_t)p * kSortChunks + c) * a.nb;
+  for (int b = threadIdx.x; b < a.nb; b += blockDim.x) {
+    a.hcnt[base + b] = cnt[b];
+    a.hsum[2 * (base + b)] = (long long)sA[b];
+    a.hsum[2 * (base + b) + 1] = (long long)sS[b];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// S2: bucket offsets, chunk offsets, exclusive bucket prefixes (one block per slice)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void sort_scan_kernel(SortArgs a) {
+  __shared__ long long sm[64];
+  const int p = blockIdx.x;
+  const int per = (a.nb + 1023) / 1024;   // buckets per thread (nb <= 2048)
+  long long cntv[2] = {0, 0}, Av[2] = {0, 0}, Sv[2] = {0, 0};
+  const int64_t base = (int64_t)p * kSortChunks * a.nb;
+  for (int q = 0; q < per; ++q) {
+    const int b = threadIdx.x * per + q;
+    if (b < a.nb) {
+      for (int c = 0; c < kSortChunks; ++c) {
+        const int64_t o = base + (int64_t)c * a.nb + b;
+        cntv[q] += a.hcnt[o];
+        Av[q] += a.hsum[2 * o];
+        Sv[q] += a.hsum[2 * o + 1];
+      }
+    }
+  }
+  long long tc, tA, tS;
+  long long ec = block_exclusive_scan(cntv[0] + cntv[1], sm, &tc);
+  long long eAx = block_exclusive_scan(Av[0] + Av[1], sm, &tA);
+  long long eSx = block_exclusive_scan(Sv[0] + Sv[1], sm, &tS);
+  uint32_t *boff = a.boff + (int64_t)p * (a.nb + 1);
+  long long *bpre = a.bpre + 2 * (int64_t)p * a.nb;
+  for (int q = 0; q < per; ++q) {
+    const int b = threadIdx.x * per + q;
+    if (b < a.nb) {
+      boff[b] = (uint32_t)ec;
+      bpre[2 * b] = eAx;
+      bpre[2 * b + 1] = eSx;
+      uint32_t run = (uint32_t)ec;
+      for (int c = 0; c < kSortChunks; ++c) {
+        const int64_t o = base + (int64_t)c * a.nb + b;
+        const uint32_t v = a.hcnt[o];
+        a.hcnt[o] = run;
+        run += v;
+      }
+    }
+    ec += cntv[q];
+    eAx += Av[q];
+    eSx += Sv[q];
+  }
+  if (threadIdx.x == 0) {
+    boff[a.nb] = (uint32_t)a.L;
+    a.tot[2 * p] = tA;
+    a.tot[2 * p + 1] = tS;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// S3: scatter (key, union index) into buckets
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(512) void sort_scatter_kernel(SortArgs a) {
+  __shared__ uint32_t cur[2048];
+  const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * kSortChunks);
+  if (work < 0) return;
+  const int p = (int)(work / kSortChunks), c = (int)(work % kSortChunks);
+  const int64_t base = ((int64_t)p * kSortChunks + c) * a.nb;
+  for (int b = threadIdx.x; b < a.nb; b += blockDim.x) cur[b] = a.hcnt[base + b];
+  __syncthreads();
+  const SliceParams sp = a.params[p];
+  const int64_t chunk = (a.L + kSortChunks - 1) / kSortChunks;
+  const int64_t l0 = c * chunk, l1 = min(a.L, l0 + chunk);
+  const float *Zp = a.Z + (int64_t)p * a.L;
+  unsigned long long *kp = a.keys + (int64_t)p * a.L;
+  for (int64_t l = l0 + threadIdx.x; l < l1; l += blockDim.x) {
+    const float z = Zp[l];
+    const int b = bucket_of(z, sp.fcmin, sp.inv_width, a.nb);
+    const uint32_t pos = atomicAdd(&cur[b], 1u);
+    kp[pos] = (unsigned long long)float_key(z) | ((unsigned long long)(uint32_t)l << 32);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// S4 helpers: stable ranking of a tile of <= kSortCap LDS entries by an 8-bit digit
+// ---------------------------------------------------------------------------
+constexpr int kR = kSortCap / 256;   // rounds of 64 per wave (16)
+
+struct RankState {
+  uint32_t hw[4][256];     // per-wave digit counts, then per-wave digit offsets
+  long long sm[64];
+  uint32_t flag;
+};
+
+// Ranks entries [0, n) of (kin, iin) by digit(d) and returns, in pos[r] for the
+// entries this thread owns (position (wid * kR + r) * 64 + lane), their offset
+// within the tile's stable counting-sort order.  If tile_tot is given it
+// receives the per-digit totals (before return, synchronised).
+template <typename DigitFn>
+__device__ __forceinline__ void rank_tile(const uint32_t *kin, const uint32_t *iin, int n, DigitFn digit,
+                                          RankState &st, int (&pos)[kR], uint32_t (&dg)[kR],
+                                          uint32_t *tile_tot) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < 4 * 256; i += 256) (&st.hw[0][0])[i] = 0;
+  __syncthreads();
+  const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int r = 0; r < kR; ++r) {
+    const int i = (wid * kR + r) * 64 + lane;
+    const bool valid = i < n;
+    const uint32_t d = valid ? digit(kin[i], iin[i]) : 0u;
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const unsigned long long bm = __ballot(valid && ((d >> bit) & 1u));
+      peers &= ((d >> bit) & 1u) ? bm : ~bm;
+    }
+    int rank = 0;
+    if (valid) {
+      const uint32_t old = st.hw[wid][d];
+      rank = (int)old + __popcll(peers & lt);
+      if ((peers & lt) == 0ull) st.hw[wid][d] = old + (uint32_t)__popcll(peers);
+    }
+    pos[r] = rank;
+    dg[r] = d;
+  }
+  __syncthreads();
+  {
+    const int d = threadIdx.x;   // 256 threads = 256 digits
+    const uint32_t c0 = st.hw[0][d], c1 = st.hw[1][d], c2 = st.hw[2][d], c3 = st.hw[3][d];
+    const long long tot = (long long)c0 + c1 + c2 + c3;
+    long long all;
+    const long long base = block_exclusive_scan(tot, st.sm, &all);
+    if (tile_tot) tile_tot[d] = (uint32_t)tot;
+    st.hw[0][d] = (uint32_t)base;
+    st.hw[1][d] = (uint32_t)(base + c0);
+    st.hw[2][d] = (uint32_t)(base + c0 + c1);
+    st.hw[3][d] = (uint32_t)(base + c0 + c1 + c2);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kR; ++r) {
+    const int i = (wid * kR + r) * 64 + lane;
+    if (i < n) pos[r] += (int)st.hw[wid][dg[r]];
+  }
+}
+
+struct GroupShared {
+  uint32_t K[2][kSortCap];
+  uint32_t I[2][kSortCap];
+  RankState rs;
+  uint32_t gbase[256], grun[256], ttot[256];
+  uint32_t red[8];
+};
+
+// One stable counting-sort pass inside LDS: (K[src], I[src]) -> (K[src^1], I[src^1]).
+template <typename DigitFn>
+__device__ __forceinline__ void lds_pass(GroupShared &g, int src, int n, DigitFn digit) {
+  int pos[kR];
+  uint32_t dg[kR];
+  rank_tile(g.K[src], g.I[src], n, digit, g.rs, pos, dg, nullptr);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t kk[kR], ii[kR];
+#pragma unroll
+  for (int r = 0; r < kR; ++r) {
+    const int i = (wid * kR + r) * 64 + lane;
+    if (i < n) {
+      kk[r] = g.K[src][i];
+      ii[r] = g.I[src][i];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kR; ++r) {
+    const int i = (wid * kR + r) * 64 + lane;
+    if (i < n) {
+      g.K[src ^ 1][pos[r]] = kk[r];
+      g.I[src ^ 1][pos[r]] = ii[r];
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int bitlen(uint32_t v) { return v ? 32 - __clz((int)v) : 0; }
+
+// block-wide min / max of n LDS values
+__device__ __forceinline__ void block_minmax(const uint32_t *v, int n, uint32_t *red, uint32_t &mn,
+                                             uint32_t &mx) {
+  uint32_t lo = 0xffffffffu, hi = 0u;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    lo = min(lo, v[i]);
+    hi = max(hi, v[i]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = min(lo, (uint32_t)__shfl_xor((int)lo, off, 64));
+    hi = max(hi, (uint32_t)__shfl_xor((int)hi, off, 64));
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[wid] = lo;
+    red[4 + wid] = hi;
+  }
+  __syncthreads();
+  mn = min(min(red[0], red[1]), min(red[2], red[3]));
+  mx = max(max(red[4], red[5]), max(red[6], red[7]));
+  __syncthreads();
+}
+
+// Fixed-point prefix scan over the sorted tile [0, n) with carry-in (cA, cS);
+// emits t at the targets and the permutation.  Returns the tile totals.
+__device__ __forceinline__ void scan_emit(const SortArgs &a, int p, const SliceParams &sp, int eA,
+                                          const uint32_t *K, const uint32_t *I, int n, int64_t out_pos,
+                                          long long &cA, long long &cS, long long Atot, long long Stot,
+                                          long long *sm) {
+  const int per = kSortCap / 256;   // 16 consecutive entries per thread
+  const int i0 = threadIdx.x * per;
+  long long fa[per], fs[per];
+  long long lA = 0, lS = 0;
+#pragma unroll
+  for (int q = 0; q < per; ++q) {
+    const int i = i0 + q;
+    fa[q] = 0;
+    fs[q] = 0;
+    if (i < n) {
+      const uint32_t idx = I[i];
+      if ((int64_t)idx >= a.M) {
+        const float v = a.w[idx - a.M];
+        const float z = key_float(K[i]);
+        fa[q] = fix_a(v, eA);
+        fs[q] = fix_s(v, z, sp.cmid, sp.eS);
+      }
+    }
+    lA += fa[q];
+    lS += fs[q];
+  }
+  long long totA, totS;
+  long long exA = block_exclusive_scan(lA, sm, &totA) + cA;
+  long long exS = block_exclusive_scan(lS, sm, &totS) + cS;
+  const double sa = ldexp(1.0, -eA), ss = ldexp(1.0, -sp.eS);
+  float *tp = a.t + (int64_t)p * a.M;
+#pragma unroll
+  for (int q = 0; q < per; ++q) {
+    const int i = i0 + q;
+    if (i < n) {
+      const uint32_t idx = I[i];
+      if ((int64_t)idx < a.M) {
+        const double zb = (double)key_float(K[i]) - sp.cmid;
+        const long long dA = 2 * exA - Atot;
+        const long long dS = 2 * exS - Stot;
+        const double tv = -a.cneg * (zb * ((double)dA * sa) - (double)dS * ss);
+        tp[idx] = (float)tv;
+      }
+      if (a.perm) a.perm[(int64_t)p * a.L + out_pos + i] = (int32_t)idx;
+    }
+    exA += fa[q];
+    exS += fs[q];
+  }
+  cA += totA;
+  cS += totS;
+}
+
+// Sort the tile's equal-key runs by union index.  Returns false if a run is
+// longer than 32 (then the caller re-sorts the whole tile by (key, index)).
+__device__ __forceinline__ bool fix_ties(uint32_t *K, uint32_t *I, int n, uint32_t *flag) {
+  if (threadIdx.x == 0) *flag = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const bool head = (i == 0) || (K[i] != K[i - 1]);
+    if (head && i + 1 < n && K[i + 1] == K[i]) {
+      int e = i + 1;
+      while (e < n && K[e] == K[i] && e - i <= 32) ++e;
+      if (e - i > 32) {
+        *flag = 1;
+      } else {
+        for (int a2 = i + 1; a2 < e; ++a2) {      // insertion sort of I[i..e)
+          const uint32_t v = I[a2];
+          int b = a2 - 1;
+          while (b >= i && I[b] > v) {
+            I[b + 1] = I[b];
+            --b;
+          }
+          I[b + 1] = v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const bool ok = (*flag == 0);
+  __syncthreads();
+  return ok;
+}
+
+__device__ __forceinline__ int lower_bound_u32(const uint32_t *arr, int n, uint32_t v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (arr[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Streaming stable LSD pass over a segment of global memory (one workgroup).
+template <typename DigitFn>
+__device__ void stream_pass(GroupShared &g, const unsigned long long *src, unsigned long long *dst, int64_t n,
+                            DigitFn digit) {
+  // global digit histogram
+  for (int i = threadIdx.x; i < 256; i += 256) g.gbase[i] = 0;
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const unsigned long long e = src[i];
+    atomicAdd(&g.gbase[digit((uint32_t)e, (uint32_t)(e >> 32))], 1u);
+  }
+  __syncthreads();
+  {
+    long long all;
+    const long long v = g.gbase[threadIdx.x];
+    const long long ex = block_exclusive_scan(v, g.rs.sm, &all);
+    g.gbase[threadIdx.x] = (uint32_t)ex;
+    g.grun[threadIdx.x] = 0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int64_t t0 = 0; t0 < n; t0 += kSortCap) {
+    const int tn = (int)min((int64_t)kSortCap, n - t0);
+    for (int i = threadIdx.x; i < tn; i += 256) {
+      const unsigned long long e = src[t0 + i];
+      g.K[0][i] = (uint32_t)e;
+      g.I[0][i] = (uint32_t)(e >> 32);
+    }
+    __syncthreads();
+    int pos[kR];
+    uint32_t dg[kR];
+    rank_tile(g.K[0], g.I[0], tn, digit, g.rs, pos, dg, g.ttot);
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      const int i = (wid * kR + r) * 64 + lane;
+      if (i < tn) {
+        const uint32_t d = dg[r];
+        const int within = pos[r] - (int)g.rs.hw[0][d];      // offset among this tile's digit-d entries
+        const int64_t o = (int64_t)g.gbase[d] + g.grun[d] + within;
+        dst[o] = (unsigned long long)g.K[0][i] | ((unsigned long long)g.I[0][i] << 32);
+      }
+    }
+    __syncthreads();
+    g.grun[threadIdx.x] += g.ttot[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void sort_group_kernel(SortArgs a) {
+  __shared__ GroupShared g;
+  const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * a.G);
+  if (work < 0) return;
+  const int p = (int)(work / a.G), grp = (int)(work % a.G);
+  const uint32_t *boff = a.boff + (int64_t)p * (a.nb + 1);
+  const int b_lo = lower_bound_u32(boff, a.nb, (uint32_t)grp * kSortHalf);
+  const int b_hi = lower_bound_u32(boff, a.nb, (uint32_t)(grp + 1) * kSortHalf);
+  if (b_lo >= b_hi) return;
+  const int64_t e_lo = boff[b_lo];
+  const int64_t e_hi = (b_hi < a.nb) ? (int64_t)boff[b_hi] : a.L;
+  const int64_t n = e_hi - e_lo;
+  if (n <= 0) return;
+  const SliceParams sp = a.params[p];
+  const int eA = (int)a.misc[1];
+  long long cA = a.bpre[2 * ((int64_t)p * a.nb + b_lo)];
+  long long cS = a.bpre[2 * ((int64_t)p * a.nb + b_lo) + 1];
+  const long long Atot = a.tot[2 * p], Stot = a.tot[2 * p + 1];
+  unsigned long long *seg = a.keys + (int64_t)p * a.L + e_lo;
+
+  if (n <= kSortCap) {
+    const int nn = (int)n;
+    for (int i = threadIdx.x; i < nn; i += 256) {
+      const unsigned long long e = seg[i];
+      g.K[0][i] = (uint32_t)e;
+      g.I[0][i] = (uint32_t)(e >> 32);
+    }
+    __syncthreads();
+    uint32_t kmin, kmax;
+    block_minmax(g.K[0], nn, g.red, kmin, kmax);
+    const int kbits = bitlen(kmax - kmin);
+    int cur = 0;
+    for (int sh = 0; sh < kbits; sh += 8) {
+      lds_pass(g, cur, nn, [=](uint32_t k, uint32_t) { return ((k - kmin) >> sh) & 255u; });
+      cur ^= 1;
+    }
+    if (!fix_ties(g.K[cur], g.I[cur], nn, &g.rs.flag)) {
+      // long runs of equal keys: stable sort by index, then by key
+      uint32_t imin, imax;
+      block_minmax(g.I[cur], nn, g.red, imin, imax);
+      const int ibits = bitlen(imax - imin);
+      for (int sh = 0; sh < ibits; sh += 8) {
+        lds_pass(g, cur, nn, [=](uint32_t, uint32_t i) { return ((i - imin) >> sh) & 255u; });
+        cur ^= 1;
+      }
+      for (int sh = 0; sh < kbits; sh += 8) {
+        lds_pass(g, cur, nn, [=](uint32_t k, uint32_t) { return ((k - kmin) >> sh) & 255u; });
+        cur ^= 1;
+      }
+    }
+    scan_emit(a, p, sp, eA, g.K[cur], g.I[cur], nn, e_lo, cA, cS, Atot, Stot, g.rs.sm);
+    return;
+  }
+
+  // Large group: stable LSD radix sort by (key, index) streaming through global memory.
+  unsigned long long *seg2 = a.keys2 + (int64_t)p * a.L + e_lo;
+  uint32_t kmin = 0xffffffffu, kmax = 0u, imin = 0xffffffffu, imax = 0u;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const unsigned long long e = seg[i];
+    kmin = min(kmin, (uint32_t)e);
+    kmax = max(kmax, (uint32_t)e);
+    imin = min(imin, (uint32_t)(e >> 32));
+    imax = max(imax, (uint32_t)(e >> 32));
+  }
+  {
+    // reduce the four values across the block through LDS
+    for (int off = 32; off > 0; off >>= 1) {
+      kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off, 64));
+      kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off, 64));
+      imin = min(imin, (uint32_t)__shfl_xor((int)imin, off, 64));
+      imax = max(imax, (uint32_t)__shfl_xor((int)imax, off, 64));
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+      g.rs.hw[0][wid] = kmin;
+      g.rs.hw[1][wid] = kmax;
+      g.rs.hw[2][wid] = imin;
+      g.rs.hw[3][wid] = imax;
+    }
+    __syncthreads();
+    kmin = min(min(g.rs.hw[0][0], g.rs.hw[0][1]), min(g.rs.hw[0][2], g.rs.hw[0][3]));
+    kmax = max(max(g.rs.hw[1][0], g.rs.hw[1][1]), max(g.rs.hw[1][2], g.rs.hw[1][3]));
+    imin = min(min(g.rs.hw[2][0], g.rs.hw[2][1]), min(g.rs.hw[2][2], g.rs.hw[2][3]));
+    imax = max(max(g.rs.hw[3][0], g.rs.hw[3][1]), max(g.rs.hw[3][2], g.rs.hw[3][3]));
+    __syncthreads();
+  }
+  const int kbits = bitlen(kmax - kmin), ibits = bitlen(imax - imin);
+  unsigned long long *src = seg, *dst = seg2;
+  for (int sh = 0; sh < ibits; sh += 8) {
+    stream_pass(g, src, dst, n, [=](uint32_t, uint32_t i) { return ((i - imin) >> sh) & 255u; });
+    unsigned long long *tmp = src; src = dst; dst = tmp;
+  }
+  for (int sh = 0; sh < kbits; sh += 8) {
+    stream_pass(g, src, dst, n, [=](uint32_t k, uint32_t) { return ((k - kmin) >> sh) & 255u; });
+    unsigned long long *tmp = src; src = dst; dst = tmp;
+  }
+  for (int64_t t0 = 0; t0 < n; t0 += kSortCap) {
+    const int tn = (int)min((int64_t)kSortCap, n - t0);
+    for (int i = threadIdx.x; i < tn; i += 256) {
+      const unsigned long long e = src[t0 + i];
+      g.K[0][i] = (uint32_t)e;
+      g.I[0][i] = (uint32_t)(e >> 32);
+    }
+    __syncthreads();
+    scan_emit(a, p, sp, eA, g.K[0], g.I[0], tn, e_lo + t0, cA, cS, Atot, Stot, g.rs.sm);
+    __syncthreads();
+  }
+}
+
+hipError_t launch_sort_path(const ExecArgs &a) {
+  const ksum_plan &pl = *a.plan;
+  const Layout &lay = *a.lay;
+  SortArgs s{};
+  s.nsl = a.nsl;
+  s.nb = lay.nb;
+  s.G = lay.sort_groups;
+  s.L = lay.L;
+  s.M = lay.M;
+  s.Z = wsp<float>(a, lay.off_z);
+  s.w = a.w;
+  s.params = wsp<SliceParams>(a, lay.off_params);
+  s.misc = wsp<double>(a, lay.off_misc);
+  s.hcnt = wsp<uint32_t>(a, lay.off_hcnt);
+  s.hsum = wsp<long long>(a, lay.off_hsum);
+  s.bpre = wsp<long long>(a, lay.off_bpre);
+  s.boff = wsp<uint32_t>(a, lay.off_boff);
+  s.tot = wsp<long long>(a, lay.off_tot);
+  s.keys = wsp<unsigned long long>(a, lay.off_keys);
+  s.keys2 = wsp<unsigned long long>(a, lay.off_keys2);
+  s.t = wsp<float>(a, pl.kernel == KSUM_LAPLACIAN ? lay.off_t2 : lay.off_t1);
+  s.perm = a.perm_out ? a.perm_out + (int64_t)a.p0 * lay.L : nullptr;
+  s.cneg = pl.sort_const;
+  const unsigned g1 = (unsigned)xcd_grid((int64_t)a.nsl * kSortChunks);
+  sort_hist_kernel<<<g1, 512, 0, a.stream>>>(s);
+  sort_scan_kernel<<<a.nsl, 1024, 0, a.stream>>>(s);
+  sort_scatter_kernel<<<g1, 512, 0, a.stream>>>(s);
+  const unsigned g4 = (unsigned)xcd_grid((int64_t)a.nsl * lay.sort_groups);
+  sort_group_kernel<<<g4, 256, 0, a.stream>>>(s);
+  return hipGetLastError();
+}
+
+}  // namespace ksum

@@ -1,0 +1,431 @@
+// C ABI of the ksum library: parameter handling, plans, workspace layout and
+// the execution schedule (one dependency chain per slice batch on the caller's
+// stream; no host synchronisation inside ksum_execute).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace ksum {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int window_degree_for(int m);
+int nfft_lanes_for(int W);
+hipError_t launch_bounds_probe(const ExecArgs &a, double *bounds_out);
+
+static ksum_status fail(ksum_status st, const std::string &msg) {
+  set_error(msg);
+  return st;
+}
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+static int64_t next_pow2(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Resolved method of a kernel: the smooth part's transform for the Fourier
+// kernels, SORT for the negative distance.
+static int resolve_method(ksum_kernel kernel, const ksum_params &p) {
+  if (kernel == KSUM_NEGDIST) return KSUM_1D_SORT;
+  if (p.method != KSUM_1D_AUTO) return p.method;
+  if (kernel == KSUM_GAUSSIAN) return p.n_coeff <= 64 ? KSUM_1D_NDFT : KSUM_1D_NFFT;
+  return KSUM_1D_NFFT;
+}
+
+static double resolve_T(ksum_kernel kernel, int method, double T) {
+  if (T > 0.0) return T;
+  if (kernel == KSUM_GAUSSIAN) return method == KSUM_1D_NDFT ? 0.045 : 0.02;
+  if (kernel == KSUM_LAPLACIAN) return 0.125;
+  return 0.0;
+}
+
+// NFFT window cells for grid n, threshold T, half-width m (one cell of margin on
+// each side of the base-cell range [floor(-nT), floor(nT)]).
+static void nfft_window(int n, double T, int m, int *lo, int *cells) {
+  const int i0lo = (int)std::floor(-(double)n * T) - 1;
+  const int i0hi = (int)std::floor((double)n * T) + 1;
+  *lo = i0lo - m + 1;
+  *cells = (i0hi + m) - *lo + 1;
+}
+
+static ksum_status validate(int32_t d, int32_t P, ksum_kernel kernel, const ksum_params &p) {
+  if (d < 1 || d > (1 << 20)) return fail(KSUM_EINVAL, "d must be in [1, 2^20]");
+  if (P < 1 || P > (1 << 24)) return fail(KSUM_EINVAL, "P must be in [1, 2^24]");
+  if (kernel != KSUM_GAUSSIAN && kernel != KSUM_LAPLACIAN && kernel != KSUM_NEGDIST)
+    return fail(KSUM_EINVAL, "unknown kernel");
+  if (p.method < KSUM_1D_AUTO || p.method > KSUM_1D_SORT) return fail(KSUM_EINVAL, "unknown method");
+  if (p.precision != KSUM_FP32 && p.precision != KSUM_SPLIT_BF16)
+    return fail(KSUM_EINVAL, "unknown precision");
+  if (p.precision == KSUM_SPLIT_BF16) return fail(KSUM_EUNSUPPORTED, "split-BF16 projection not built");
+  if (p.slice_batch < 0) return fail(KSUM_EINVAL, "slice_batch must be >= 0");
+  if (p.device < 0) return fail(KSUM_EINVAL, "device must be >= 0");
+  if (kernel == KSUM_NEGDIST) {
+    if (p.method != KSUM_1D_AUTO && p.method != KSUM_1D_SORT)
+      return fail(KSUM_EUNSUPPORTED, "the negative distance kernel uses the sort method");
+    return KSUM_OK;
+  }
+  if (!(p.sigma > 0.0) || !std::isfinite(p.sigma)) return fail(KSUM_EINVAL, "sigma must be finite and > 0");
+  if (p.n_coeff < 2 || p.n_coeff > 4096 || (p.n_coeff & 1))
+    return fail(KSUM_EINVAL, "n_coeff must be even and in [2, 4096]");
+  if (!(p.coeff_eps >= 0.0)) return fail(KSUM_EINVAL, "coeff_eps must be >= 0");
+  if (!(p.T >= 0.0 && p.T < 0.25)) return fail(KSUM_EINVAL, "T must satisfy 0 < T < 0.25 (0 = default)");
+  if (p.method == KSUM_1D_SORT) return fail(KSUM_EUNSUPPORTED, "this kernel has no pure sort method");
+  const int method = resolve_method(kernel, p);
+  if (method == KSUM_1D_NFFT) {
+    if (p.oversample < 2 || p.oversample > 8) return fail(KSUM_EINVAL, "oversample must be in [2, 8]");
+    if (p.window_m < 2 || p.window_m > 8) return fail(KSUM_EINVAL, "window_m must be in [2, 8]");
+    const int64_t n = (int64_t)p.oversample * p.n_coeff;
+    if (n > 8192 || (n & (n - 1))) return fail(KSUM_EUNSUPPORTED, "NFFT grid must be a power of two <= 8192");
+    int lo, cells;
+    nfft_window((int)n, resolve_T(kernel, method, p.T), p.window_m, &lo, &cells);
+    if (cells > n) return fail(KSUM_EUNSUPPORTED, "NFFT window wider than the grid (T too large)");
+    if ((size_t)cells * 64 * sizeof(float) > 160 * 1024)
+      return fail(KSUM_EUNSUPPORTED, "NFFT window does not fit LDS");
+  }
+  return KSUM_OK;
+}
+
+Layout make_layout(const ksum_plan &pl, int64_t N, int64_t M) {
+  Layout y;
+  y.N = N;
+  y.M = M;
+  y.L = N + M;
+  y.B = pl.params.slice_batch > 0 ? std::min(pl.params.slice_batch, pl.P) : pl.P;
+  const int64_t B = y.B;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  y.off_misc = take(8 * sizeof(double));
+  y.off_wpart = take(kWsumBlocks * sizeof(double));
+  y.off_params = take(B * sizeof(SliceParams));
+  y.off_bounds = take(B * 2 * sizeof(uint32_t));
+  y.off_z = take((size_t)B * y.L * sizeof(float));
+  y.off_t1 = take((size_t)B * M * sizeof(float));
+  y.off_t2 = (pl.kernel == KSUM_LAPLACIAN) ? take((size_t)B * M * sizeof(float)) : y.off_t1;
+  y.off_sacc = take((size_t)M * sizeof(double));
+  y.off_wf = take((size_t)N * sizeof(float));
+  if (pl.use_fourier) {
+    y.off_coef = take((size_t)B * (pl.K + 1) * sizeof(float));
+    if (pl.method == KSUM_1D_NDFT) {
+      y.ndft_chunks = (int32_t)((N + 4095) / 4096);
+      y.off_fpart = take((size_t)B * y.ndft_chunks * (pl.K + 1) * sizeof(float2));
+    } else {
+      nfft_window(pl.n_grid, pl.params.T, pl.params.window_m, &y.win_lo, &y.win_cells);
+      const int lanes = nfft_lanes_for(y.win_cells);
+      y.nfft_chunks = (int32_t)((N + (int64_t)lanes * 16 - 1) / ((int64_t)lanes * 16));
+      y.off_fpart = take((size_t)B * y.nfft_chunks * y.win_cells * sizeof(float));
+      y.off_grid = take((size_t)B * y.win_cells * sizeof(float));
+    }
+    if (pl.kernel == KSUM_LAPLACIAN) y.off_lapv = take((size_t)B * pl.lap_L * sizeof(double));
+  }
+  if (pl.use_sort) {
+    const int64_t L = y.L;
+    y.nb = (int32_t)std::min<int64_t>(2048, std::max<int64_t>(64, next_pow2((L + 127) / 128)));
+    y.sort_groups = (int32_t)((L + kSortHalf - 1) / kSortHalf + 1);
+    y.off_hcnt = take((size_t)B * kSortChunks * y.nb * sizeof(uint32_t));
+    y.off_hsum = take((size_t)B * kSortChunks * y.nb * 2 * sizeof(long long));
+    y.off_bpre = take((size_t)B * y.nb * 2 * sizeof(long long));
+    y.off_boff = take((size_t)B * (y.nb + 1) * sizeof(uint32_t));
+    y.off_tot = take((size_t)B * 2 * sizeof(long long));
+    y.off_keys = take((size_t)B * L * sizeof(unsigned long long));
+    y.off_keys2 = take((size_t)B * L * sizeof(unsigned long long));
+  }
+  y.total = o;
+  return y;
+}
+
+static void fill_defaults(ksum_kernel kernel, ksum_params *p) {
+  std::memset(p, 0, sizeof(*p));
+  p->sigma = 1.0;
+  p->seed = 0;
+  p->directions = nullptr;
+  p->n_coeff = (kernel == KSUM_LAPLACIAN) ? 256 : 64;
+  p->coeff_eps = 0.0;
+  p->T = 0.0;
+  p->oversample = 2;
+  p->window_m = 6;
+  p->method = KSUM_1D_AUTO;
+  p->precision = KSUM_FP32;
+  p->slice_batch = 0;
+  p->device = 0;
+}
+
+static void free_plan(ksum_plan *pl) {
+  if (!pl) return;
+  if (pl->d_dirs) (void)hipFree(pl->d_dirs);
+  if (pl->d_deconv) (void)hipFree(pl->d_deconv);
+  if (pl->d_twiddle) (void)hipFree(pl->d_twiddle);
+  if (pl->d_costab) (void)hipFree(pl->d_costab);
+  delete pl;
+}
+
+}  // namespace ksum
+
+using namespace ksum;
+
+extern "C" {
+
+const char *ksum_version(void) { return "ksum 0.1.0 (gfx950)"; }
+
+const char *ksum_status_string(ksum_status st) {
+  switch (st) {
+    case KSUM_OK: return "KSUM_OK";
+    case KSUM_EINVAL: return "KSUM_EINVAL";
+    case KSUM_EUNSUPPORTED: return "KSUM_EUNSUPPORTED";
+    case KSUM_ENOMEM: return "KSUM_ENOMEM";
+    case KSUM_EWORKSPACE: return "KSUM_EWORKSPACE";
+    case KSUM_ENONFINITE: return "KSUM_ENONFINITE";
+    case KSUM_EDEVICE: return "KSUM_EDEVICE";
+  }
+  return "KSUM_UNKNOWN";
+}
+
+const char *ksum_last_error(void) { return g_last_error.c_str(); }
+
+ksum_status ksum_params_default(ksum_kernel kernel, ksum_params *out) {
+  if (!out) return fail(KSUM_EINVAL, "out is NULL");
+  if (kernel != KSUM_GAUSSIAN && kernel != KSUM_LAPLACIAN && kernel != KSUM_NEGDIST)
+    return fail(KSUM_EINVAL, "unknown kernel");
+  fill_defaults(kernel, out);
+  return KSUM_OK;
+}
+
+ksum_status ksum_check_params(int32_t d, int32_t P, ksum_kernel kernel, const ksum_params *params) {
+  ksum_params p;
+  if (params) p = *params; else fill_defaults(kernel, &p);
+  return validate(d, P, kernel, p);
+}
+
+ksum_status ksum_generate_directions(int32_t d, int32_t P, uint64_t seed, double *host_out) {
+  if (d < 1 || P < 1) return fail(KSUM_EINVAL, "d and P must be >= 1");
+  if (!host_out) return fail(KSUM_EINVAL, "host_out is NULL");
+  generate_directions(d, P, seed, host_out);
+  return KSUM_OK;
+}
+
+// Fills the host-side fields of a plan (no device access).
+static ksum_status plan_host_setup(int32_t d, int32_t P, ksum_kernel kernel, const ksum_params *params,
+                                   ksum_plan *pl) {
+  ksum_params p;
+  if (params) p = *params; else fill_defaults(kernel, &p);
+  const ksum_status st = validate(d, P, kernel, p);
+  if (st != KSUM_OK) return st;
+  pl->d = d;
+  pl->P = P;
+  pl->kernel = kernel;
+  pl->method = resolve_method(kernel, p);
+  p.T = resolve_T(kernel, pl->method, p.T);
+  pl->params = p;
+  pl->params.directions = nullptr;
+  pl->use_sort = (kernel == KSUM_NEGDIST || kernel == KSUM_LAPLACIAN);
+  pl->use_fourier = (kernel != KSUM_NEGDIST);
+  pl->d_pad = (int32_t)((d + kGemmBK - 1) / kGemmBK * kGemmBK);
+  pl->P_pad = (int32_t)((P + kGemmBM - 1) / kGemmBM * kGemmBM + kGemmBM);
+  pl->cd = std::sqrt(M_PI) * std::exp(std::lgamma((d + 1) / 2.0) - std::lgamma(d / 2.0));
+  pl->sort_const = (kernel == KSUM_LAPLACIAN) ? pl->cd / p.sigma : pl->cd;
+  pl->gauss_logc = std::log((double)d * M_PI / std::sqrt(2.0)) - std::lgamma((d + 2) / 2.0);
+  if (pl->use_fourier) {
+    pl->K = (pl->method == KSUM_1D_NDFT) ? p.n_coeff / 2 : p.n_coeff / 2 - 1;
+    if (pl->method == KSUM_1D_NFFT) pl->n_grid = p.oversample * p.n_coeff;
+    if (kernel == KSUM_LAPLACIAN) pl->lap_L = 16 * p.n_coeff;
+  }
+  pl->dirs.resize((size_t)P * d);
+  if (params && params->directions) {
+    std::memcpy(pl->dirs.data(), params->directions, sizeof(double) * (size_t)P * d);
+  } else {
+    generate_directions(d, P, p.seed, pl->dirs.data());
+  }
+  if (pl->method == KSUM_1D_NFFT) {
+    std::string err;
+    if (!build_window_poly(p.window_m, pl->n_grid, p.oversample, &pl->poly, &err))
+      return fail(KSUM_EUNSUPPORTED, err);
+  }
+  return KSUM_OK;
+}
+
+ksum_status ksum_workspace_bytes(int32_t d, int32_t P, ksum_kernel kernel, const ksum_params *params,
+                                 int64_t N, int64_t M, size_t *bytes) {
+  if (!bytes) return fail(KSUM_EINVAL, "bytes is NULL");
+  if (N < 1 || M < 1) return fail(KSUM_EINVAL, "N and M must be >= 1");
+  if (N + M > 0x7fffffffLL) return fail(KSUM_EUNSUPPORTED, "N + M must be < 2^31");
+  ksum_plan tmp;
+  ksum_params p;
+  if (params) p = *params; else fill_defaults(kernel, &p);
+  p.directions = nullptr;   // the directions do not change the size
+  const ksum_status st = plan_host_setup(d, P, kernel, &p, &tmp);
+  if (st != KSUM_OK) return st;
+  *bytes = make_layout(tmp, N, M).total;
+  return KSUM_OK;
+}
+
+ksum_status ksum_plan_create(int32_t d, int32_t P, ksum_kernel kernel, const ksum_params *params,
+                             ksum_plan **out) {
+  if (!out) return fail(KSUM_EINVAL, "out is NULL");
+  *out = nullptr;
+  ksum_plan *pl = new (std::nothrow) ksum_plan();
+  if (!pl) return fail(KSUM_ENOMEM, "host allocation failed");
+  ksum_status st = plan_host_setup(d, P, kernel, params, pl);
+  if (st != KSUM_OK) {
+    free_plan(pl);
+    return st;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= pl->params.device) {
+    free_plan(pl);
+    return fail(KSUM_EDEVICE, "no HIP device with the requested ordinal");
+  }
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  if (hipSetDevice(pl->params.device) != hipSuccess) {
+    free_plan(pl);
+    return fail(KSUM_EDEVICE, "hipSetDevice failed");
+  }
+  auto dev_fail = [&](ksum_status s, const char *what) {
+    free_plan(pl);
+    (void)hipSetDevice(prev);
+    return fail(s, what);
+  };
+  // directions, FP32, zero padded to [P_pad][d_pad]
+  std::vector<float> hd((size_t)pl->P_pad * pl->d_pad, 0.f);
+  for (int32_t p = 0; p < P; ++p)
+    for (int32_t i = 0; i < d; ++i) hd[(size_t)p * pl->d_pad + i] = (float)pl->dirs[(size_t)p * d + i];
+  if (hipMalloc(&pl->d_dirs, hd.size() * sizeof(float)) != hipSuccess) return dev_fail(KSUM_ENOMEM, "hipMalloc");
+  if (hipMemcpy(pl->d_dirs, hd.data(), hd.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+    return dev_fail(KSUM_EDEVICE, "hipMemcpy");
+  if (pl->method == KSUM_1D_NFFT) {
+    const int n = pl->n_grid, m = pl->params.window_m, os = pl->params.oversample;
+    // window normalised to phi(0) = 1 in the polynomials; deconvolution 1/(n phihat/phi0)^2
+    const double b = M_PI * (2.0 - 1.0 / os);
+    const double phi0 = std::sinh(b * m) / (M_PI * m);
+    std::vector<float> dc(pl->K + 1);
+    for (int k = 0; k <= pl->K; ++k) {
+      const double ph = (double)n * kb_phihat(m, n, os, k) / phi0;
+      dc[k] = (float)(1.0 / (ph * ph));
+    }
+    std::vector<float2> tw(n);
+    for (int j = 0; j < n; ++j) {
+      const double ang = -2.0 * M_PI * (double)j / (double)n;
+      tw[j] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    if (hipMalloc(&pl->d_deconv, dc.size() * sizeof(float)) != hipSuccess ||
+        hipMalloc(&pl->d_twiddle, tw.size() * sizeof(float2)) != hipSuccess)
+      return dev_fail(KSUM_ENOMEM, "hipMalloc");
+    if (hipMemcpy(pl->d_deconv, dc.data(), dc.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pl->d_twiddle, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
+      return dev_fail(KSUM_EDEVICE, "hipMemcpy");
+  }
+  if (pl->kernel == KSUM_LAPLACIAN) {
+    std::vector<double> ct(pl->lap_L);
+    for (int j = 0; j < pl->lap_L; ++j) ct[j] = std::cos(2.0 * M_PI * (double)j / (double)pl->lap_L);
+    if (hipMalloc(&pl->d_costab, ct.size() * sizeof(double)) != hipSuccess) return dev_fail(KSUM_ENOMEM, "hipMalloc");
+    if (hipMemcpy(pl->d_costab, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      return dev_fail(KSUM_EDEVICE, "hipMemcpy");
+  }
+  (void)hipSetDevice(prev);
+  *out = pl;
+  return KSUM_OK;
+}
+
+ksum_status ksum_plan_destroy(ksum_plan *plan) {
+  if (!plan) return KSUM_OK;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(plan->params.device);
+  (void)hipDeviceSynchronize();
+  free_plan(plan);
+  (void)hipSetDevice(prev);
+  return KSUM_OK;
+}
+
+ksum_status ksum_get_directions(const ksum_plan *plan, double *host_out) {
+  if (!plan || !host_out) return fail(KSUM_EINVAL, "null argument");
+  std::memcpy(host_out, plan->dirs.data(), sizeof(double) * plan->dirs.size());
+  return KSUM_OK;
+}
+
+ksum_status ksum_workspace_size(const ksum_plan *plan, int64_t N, int64_t M, size_t *bytes) {
+  if (!plan || !bytes) return fail(KSUM_EINVAL, "null argument");
+  if (N < 1 || M < 1) return fail(KSUM_EINVAL, "N and M must be >= 1");
+  if (N + M > 0x7fffffffLL) return fail(KSUM_EUNSUPPORTED, "N + M must be < 2^31");
+  *bytes = make_layout(*plan, N, M).total;
+  return KSUM_OK;
+}
+
+static ksum_status execute_impl(ksum_plan *plan, const void *x, int64_t N, const void *y, int64_t M,
+                                const void *w, bool f64, float *s, void *ws, size_t ws_bytes, void *stream,
+                                const ksum_probe *probe) {
+  if (!plan) return fail(KSUM_EINVAL, "plan is NULL");
+  if (!x || !y || !w || !s || !ws) return fail(KSUM_EINVAL, "null device pointer");
+  if (N < 1 || M < 1) return fail(KSUM_EINVAL, "N and M must be >= 1");
+  if (N + M > 0x7fffffffLL) return fail(KSUM_EUNSUPPORTED, "N + M must be < 2^31");
+  const Layout lay = make_layout(*plan, N, M);
+  if (ws_bytes < lay.total) return fail(KSUM_EWORKSPACE, "workspace too small");
+  if ((uintptr_t)ws % 256 != 0) return fail(KSUM_EINVAL, "workspace must be 256-byte aligned");
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  if (prev != plan->params.device && hipSetDevice(plan->params.device) != hipSuccess)
+    return fail(KSUM_EDEVICE, "hipSetDevice failed");
+  ExecArgs a{};
+  a.plan = plan;
+  a.lay = &lay;
+  a.ws = static_cast<char *>(ws);
+  a.stream = static_cast<hipStream_t>(stream);
+  a.x = x;
+  a.y = y;
+  a.f64in = f64;
+  a.want_perm = probe && probe->perm;
+  a.perm_out = probe ? probe->perm : nullptr;
+  a.t_out = probe ? probe->t : nullptr;
+  a.w = f64 ? wsp<float>(a, lay.off_wf) : static_cast<const float *>(w);
+  hipError_t e = launch_weight_prep(a, f64 ? static_cast<const double *>(w) : nullptr);
+  for (int32_t p0 = 0; p0 < plan->P && e == hipSuccess; p0 += lay.B) {
+    a.p0 = p0;
+    a.nsl = std::min(lay.B, plan->P - p0);
+    e = launch_projection(a);
+    if (e == hipSuccess) e = launch_slice_setup(a);
+    if (e == hipSuccess && probe && probe->z)
+      e = hipMemcpyAsync(probe->z + (int64_t)p0 * lay.L, a.ws + lay.off_z, (size_t)a.nsl * lay.L * sizeof(float),
+                         hipMemcpyDeviceToDevice, a.stream);
+    if (e == hipSuccess && probe && probe->bounds) e = launch_bounds_probe(a, probe->bounds);
+    if (e == hipSuccess && plan->use_fourier)
+      e = (plan->method == KSUM_1D_NDFT) ? launch_ndft(a) : launch_nfft(a);
+    if (e == hipSuccess && plan->use_sort) e = launch_sort_path(a);
+    if (e == hipSuccess) e = launch_accumulate(a, s, p0 == 0, p0 + a.nsl >= plan->P);
+  }
+  if (prev != plan->params.device) (void)hipSetDevice(prev);
+  if (e != hipSuccess) return fail(KSUM_EDEVICE, std::string("HIP launch failed: ") + hipGetErrorString(e));
+  return KSUM_OK;
+}
+
+ksum_status ksum_execute(ksum_plan *plan, const float *x, int64_t N, const float *y, int64_t M, const float *w,
+                         float *s, void *ws, size_t ws_bytes, void *stream) {
+  return execute_impl(plan, x, N, y, M, w, false, s, ws, ws_bytes, stream, nullptr);
+}
+
+ksum_status ksum_execute_f64in(ksum_plan *plan, const double *x, int64_t N, const double *y, int64_t M,
+                               const double *w, float *s, void *ws, size_t ws_bytes, void *stream) {
+  return execute_impl(plan, x, N, y, M, w, true, s, ws, ws_bytes, stream, nullptr);
+}
+
+ksum_status ksum_execute_probe(ksum_plan *plan, const float *x, int64_t N, const float *y, int64_t M,
+                               const float *w, float *s, void *ws, size_t ws_bytes, void *stream,
+                               const ksum_probe *probe) {
+  return execute_impl(plan, x, N, y, M, w, false, s, ws, ws_bytes, stream, probe);
+}
+
+}  // extern "C"
