@@ -194,6 +194,17 @@ ksum_status ksum_execute_probe(ksum_plan *plan, const float *x, int64_t N, const
                                const float *w, float *s, void *ws, size_t ws_bytes, void *stream,
                                const ksum_probe *probe);
 
+/* Per-kernel timing (diagnostic).  While enabled, ksum_execute records HIP events
+ * on its stream around every kernel it launches (a few microseconds of overhead
+ * per kernel); ksum_stage_times synchronises with the last event and returns,
+ * for each stage, the accumulated milliseconds and the number of launches since
+ * timing was enabled.  Not thread-safe: time one execution stream at a time.
+ * Stages are numbered 0..ksum_stage_count()-1 and named by ksum_stage_name(). */
+ksum_status ksum_set_timing(ksum_plan *plan, int32_t enable);
+ksum_status ksum_stage_times(ksum_plan *plan, double *ms_out, int64_t *calls_out);
+int32_t ksum_stage_count(void);
+const char *ksum_stage_name(int32_t stage);
+
 #ifdef __cplusplus
 }
 #endif

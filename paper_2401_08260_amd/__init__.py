@@ -66,6 +66,10 @@ _sigs = {
                                           _P]),
     "ksum_execute_probe": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P, ctypes.c_size_t,
                                           _P, ctypes.POINTER(ksum_probe)]),
+    "ksum_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "ksum_stage_times": (ctypes.c_int, [_P, _P, _P]),
+    "ksum_stage_count": (ctypes.c_int32, []),
+    "ksum_stage_name": (ctypes.c_char_p, [ctypes.c_int32]),
 }
 for _name, (_res, _args) in _sigs.items():
     _fn = getattr(_lib, _name)
@@ -178,6 +182,27 @@ def ksum_execute_probe(plan: int, x: int, N: int, y: int, M: int, w: int, s: int
                        stream: int, probe: Optional[ksum_probe]) -> None:
     _check(_lib.ksum_execute_probe(plan, x, N, y, M, w, s, ws, ws_bytes, stream,
                                    ctypes.byref(probe) if probe is not None else None), "ksum_execute_probe")
+
+
+def ksum_set_timing(plan: int, enable: bool) -> None:
+    _check(_lib.ksum_set_timing(plan, 1 if enable else 0), "ksum_set_timing")
+
+
+def ksum_stage_count() -> int:
+    return _lib.ksum_stage_count()
+
+
+def ksum_stage_name(stage: int) -> str:
+    return _lib.ksum_stage_name(stage).decode()
+
+
+def ksum_stage_times(plan: int) -> dict:
+    """{stage name: (total ms, launches)} accumulated since timing was enabled."""
+    n = ksum_stage_count()
+    ms = np.zeros(n, dtype=np.float64)
+    calls = np.zeros(n, dtype=np.int64)
+    _check(_lib.ksum_stage_times(plan, ms.ctypes.data, calls.ctypes.data), "ksum_stage_times")
+    return {ksum_stage_name(i): (float(ms[i]), int(calls[i])) for i in range(n)}
 
 
 # ---------------------------------------------------------------------------

@@ -46,7 +46,20 @@ struct SliceParams {
   int32_t pad;
 };
 
-struct ksum_plan_impl;  // forward
+// Kernel stages that can be timed with HIP events (ksum_set_timing).
+enum StageId {
+  ST_MISC = 0, ST_PROJECT, ST_SETUP, ST_NDFT_ADJOINT, ST_NDFT_FORWARD, ST_NFFT_SPREAD, ST_NFFT_GRID,
+  ST_NFFT_INTERP, ST_SORT_HIST, ST_SORT_SCAN, ST_SORT_SCATTER, ST_SORT_GROUP, ST_ACCUMULATE, ST_COUNT
+};
+
+struct Timer {
+  int device = 0;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ids;
+  int used = 0;
+  double ms[ST_COUNT] = {};
+  long long calls[ST_COUNT] = {};
+};
 
 }  // namespace ksum
 
@@ -72,6 +85,7 @@ struct ksum_plan {
   float *d_deconv = nullptr;     // [K+1] 1 / (n phihat(k))^2 (NFFT)
   float2 *d_twiddle = nullptr;   // [n_grid] exp(-2 pi i j / n)
   double *d_costab = nullptr;    // [lap_L] cos(2 pi j / lap_L)
+  ksum::Timer *timer = nullptr;  // stage timing (diagnostic), null when off
 };
 
 namespace ksum {
@@ -136,6 +150,14 @@ struct ExecArgs {
 
 template <typename T> inline T *wsp(const ExecArgs &a, size_t off) {
   return reinterpret_cast<T *>(a.ws + off);
+}
+
+// Records a timing event on the execution stream: the interval up to the next
+// mark is attributed to `stage` (stage < 0 closes the interval).
+inline void mark(const ExecArgs &a, int stage) {
+  Timer *t = a.plan->timer;
+  if (!t || t->used >= (int)t->ev.size()) return;
+  if (hipEventRecord(t->ev[t->used], a.stream) == hipSuccess) t->ids[t->used++] = stage;
 }
 
 hipError_t launch_weight_prep(const ExecArgs &a, const double *w64);

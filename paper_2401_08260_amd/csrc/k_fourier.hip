@@ -142,9 +142,11 @@ hipError_t launch_ndft(const ExecArgs &a) {
   f.coef = wsp<float>(a, lay.off_coef);
   f.part = wsp<float2>(a, lay.off_fpart);
   f.t = wsp<float>(a, lay.off_t1);
+  mark(a, ST_NDFT_ADJOINT);
   ndft_adjoint_kernel<<<(unsigned)xcd_grid((int64_t)a.nsl * f.chunks), 256, 0, a.stream>>>(f);
   const int ychunk = 2048;
   const int nyc = (int)((lay.M + ychunk - 1) / ychunk);
+  mark(a, ST_NDFT_FORWARD);
   ndft_forward_kernel<<<(unsigned)xcd_grid((int64_t)a.nsl * nyc), 256, (pl.K + 1) * sizeof(float2),
                         a.stream>>>(f, ychunk);
   return hipGetLastError();
@@ -323,10 +325,13 @@ static void launch_nfft_m(const FourierArgs &f, const ExecArgs &a) {
   if (grid_lds > 65536)
     (void)hipFuncSetAttribute((const void *)nfft_grid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)grid_lds);
+  mark(a, ST_NFFT_SPREAD);
   nfft_spread_kernel<MW, DEG><<<gs, f.lanes, spread_lds, a.stream>>>(f);
+  mark(a, ST_NFFT_GRID);
   nfft_grid_kernel<<<a.nsl, 256, grid_lds, a.stream>>>(f);
   const int ychunk = 4096;
   const int nyc = (int)((f.M + ychunk - 1) / ychunk);
+  mark(a, ST_NFFT_INTERP);
   nfft_interp_kernel<MW, DEG><<<(unsigned)xcd_grid((int64_t)a.nsl * nyc), 256, (size_t)f.W * sizeof(float),
                                 a.stream>>>(f, ychunk);
 }

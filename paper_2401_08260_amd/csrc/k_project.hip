@@ -195,7 +195,9 @@ hipError_t launch_projection(const ExecArgs &a) {
   const Layout &lay = *a.lay;
   uint32_t *bounds = wsp<uint32_t>(a, lay.off_bounds);
   float *Z = wsp<float>(a, lay.off_z);
+  mark(a, ST_MISC);
   bounds_init_kernel<<<(a.nsl + 255) / 256, 256, 0, a.stream>>>(bounds, a.nsl);
+  mark(a, ST_PROJECT);
   const int n_col = (int)((lay.L + BN - 1) / BN);
   const int n_row = (a.nsl + BM - 1) / BM;
   const int64_t grid = xcd_grid((int64_t)n_col * n_row);
@@ -254,6 +256,7 @@ hipError_t launch_weight_prep(const ExecArgs &a, const double *w64) {
   const Layout &lay = *a.lay;
   double *part = wsp<double>(a, lay.off_wpart);
   double *misc = wsp<double>(a, lay.off_misc);
+  mark(a, ST_MISC);
   if (w64) {
     float *wf = wsp<float>(a, lay.off_wf);
     wsum_partial_kernel<double><<<kWsumBlocks, 256, 0, a.stream>>>(w64, lay.N, wf, part);

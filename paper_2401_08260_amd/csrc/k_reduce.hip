@@ -31,6 +31,7 @@ hipError_t launch_accumulate(const ExecArgs &a, float *s, bool first, bool last)
   double *sacc = wsp<double>(a, lay.off_sacc);
   float *tout = a.t_out ? a.t_out + (int64_t)a.p0 * lay.M : nullptr;
   const unsigned grid = (unsigned)((lay.M + 255) / 256);
+  mark(a, ST_ACCUMULATE);
   accumulate_kernel<<<grid, 256, 0, a.stream>>>(t1, t2, a.nsl, lay.M, sacc, s, tout, first ? 1 : 0,
                                                 last ? 1 : 0, 1.0 / (double)pl.P);
   return hipGetLastError();

@@ -158,6 +158,7 @@ hipError_t launch_slice_setup(const ExecArgs &a) {
   s.coef = wsp<float>(a, lay.off_coef);
   s.lapv = wsp<double>(a, lay.off_lapv);
   s.bounds_out = nullptr;
+  mark(a, ST_SETUP);
   slice_setup_kernel<<<a.nsl, 256, 0, a.stream>>>(s);
   return hipGetLastError();
 }
@@ -178,6 +179,7 @@ hipError_t launch_bounds_probe(const ExecArgs &a, double *bounds_out) {
   s.misc = wsp<double>(a, lay.off_misc);
   s.params = wsp<SliceParams>(a, lay.off_params);
   s.bounds_out = bounds_out + 2 * (int64_t)a.p0;
+  mark(a, ST_MISC);
   slice_setup_kernel<<<a.nsl, 64, 0, a.stream>>>(s);
   return hipGetLastError();
 }

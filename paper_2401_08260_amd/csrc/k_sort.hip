@@ -575,10 +575,14 @@ hipError_t launch_sort_path(const ExecArgs &a) {
   s.perm = a.perm_out ? a.perm_out + (int64_t)a.p0 * lay.L : nullptr;
   s.cneg = pl.sort_const;
   const unsigned g1 = (unsigned)xcd_grid((int64_t)a.nsl * kSortChunks);
+  mark(a, ST_SORT_HIST);
   sort_hist_kernel<<<g1, 512, 0, a.stream>>>(s);
+  mark(a, ST_SORT_SCAN);
   sort_scan_kernel<<<a.nsl, 1024, 0, a.stream>>>(s);
+  mark(a, ST_SORT_SCATTER);
   sort_scatter_kernel<<<g1, 512, 0, a.stream>>>(s);
   const unsigned g4 = (unsigned)xcd_grid((int64_t)a.nsl * lay.sort_groups);
+  mark(a, ST_SORT_GROUP);
   sort_group_kernel<<<g4, 256, 0, a.stream>>>(s);
   return hipGetLastError();
 }

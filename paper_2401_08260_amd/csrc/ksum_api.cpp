@@ -165,8 +165,16 @@ static void fill_defaults(ksum_kernel kernel, ksum_params *p) {
   p->device = 0;
 }
 
+static void free_timer(ksum_plan *pl) {
+  if (!pl->timer) return;
+  for (hipEvent_t e : pl->timer->ev) (void)hipEventDestroy(e);
+  delete pl->timer;
+  pl->timer = nullptr;
+}
+
 static void free_plan(ksum_plan *pl) {
   if (!pl) return;
+  free_timer(pl);
   if (pl->d_dirs) (void)hipFree(pl->d_dirs);
   if (pl->d_deconv) (void)hipFree(pl->d_deconv);
   if (pl->d_twiddle) (void)hipFree(pl->d_twiddle);
@@ -407,6 +415,7 @@ static ksum_status execute_impl(ksum_plan *plan, const void *x, int64_t N, const
     if (e == hipSuccess && plan->use_sort) e = launch_sort_path(a);
     if (e == hipSuccess) e = launch_accumulate(a, s, p0 == 0, p0 + a.nsl >= plan->P);
   }
+  mark(a, -1);
   if (prev != plan->params.device) (void)hipSetDevice(prev);
   if (e != hipSuccess) return fail(KSUM_EDEVICE, std::string("HIP launch failed: ") + hipGetErrorString(e));
   return KSUM_OK;
@@ -426,6 +435,75 @@ ksum_status ksum_execute_probe(ksum_plan *plan, const float *x, int64_t N, const
                                const float *w, float *s, void *ws, size_t ws_bytes, void *stream,
                                const ksum_probe *probe) {
   return execute_impl(plan, x, N, y, M, w, false, s, ws, ws_bytes, stream, probe);
+}
+
+static const char *kStageNames[ST_COUNT] = {
+    "misc", "project", "setup", "ndft_adjoint", "ndft_forward", "nfft_spread", "nfft_grid",
+    "nfft_interp", "sort_hist", "sort_scan", "sort_scatter", "sort_group", "accumulate"};
+
+int32_t ksum_stage_count(void) { return ST_COUNT; }
+
+const char *ksum_stage_name(int32_t stage) {
+  return (stage >= 0 && stage < ST_COUNT) ? kStageNames[stage] : "";
+}
+
+ksum_status ksum_set_timing(ksum_plan *plan, int32_t enable) {
+  if (!plan) return fail(KSUM_EINVAL, "plan is NULL");
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(plan->params.device);
+  (void)hipDeviceSynchronize();
+  free_timer(plan);
+  ksum_status st = KSUM_OK;
+  if (enable) {
+    Timer *t = new (std::nothrow) Timer();
+    if (!t) {
+      st = fail(KSUM_ENOMEM, "host allocation failed");
+    } else {
+      t->device = plan->params.device;
+      t->ev.resize(4096);
+      t->ids.resize(4096);
+      for (auto &e : t->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+          e = nullptr;
+          st = fail(KSUM_EDEVICE, "hipEventCreate failed");
+          break;
+        }
+      }
+      if (st != KSUM_OK) {
+        for (hipEvent_t e : t->ev)
+          if (e) (void)hipEventDestroy(e);
+        delete t;
+      } else {
+        plan->timer = t;
+      }
+    }
+  }
+  (void)hipSetDevice(prev);
+  return st;
+}
+
+ksum_status ksum_stage_times(ksum_plan *plan, double *ms_out, int64_t *calls_out) {
+  if (!plan || !ms_out) return fail(KSUM_EINVAL, "null argument");
+  Timer *t = plan->timer;
+  if (!t) return fail(KSUM_EINVAL, "timing is not enabled");
+  if (t->used > 0) {
+    if (hipEventSynchronize(t->ev[t->used - 1]) != hipSuccess) return fail(KSUM_EDEVICE, "hipEventSynchronize");
+    for (int i = 0; i + 1 < t->used; ++i) {
+      const int id = t->ids[i];
+      if (id < 0) continue;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, t->ev[i], t->ev[i + 1]) != hipSuccess) return fail(KSUM_EDEVICE, "elapsed");
+      t->ms[id] += ms;
+      t->calls[id] += 1;
+    }
+    t->used = 0;
+  }
+  for (int i = 0; i < ST_COUNT; ++i) {
+    ms_out[i] = t->ms[i];
+    if (calls_out) calls_out[i] = t->calls[i];
+  }
+  return KSUM_OK;
 }
 
 }  // extern "C"
