@@ -20,7 +20,10 @@ constexpr int kMaxTaps = 16;        // 2 * window_m, window_m <= 8
 constexpr int kMaxPolyDeg = 13;     // degree of the per-tap window polynomials
 constexpr int kGemmBK = 16;         // K step of the projection GEMM (d is padded to it)
 constexpr int kGemmBM = 128;        // slices per GEMM tile (P is padded to it)
-constexpr int kSortChunks = 8;      // chunks per slice in the bucket histogram / scatter
+constexpr int kGemmBlocksPerCU = 3; // persistent projection blocks per CU
+constexpr int kMaxBatch = 1024;     // slices per batch (per-block min / max live in LDS)
+constexpr int kSortChunks = 16;     // chunks per slice in the bucket histogram / scatter
+constexpr int kNfftPPL = 64;        // sources per lane in an NFFT spread block
 constexpr int kSortCap = 4096;      // elements a bucket group may hold to be sorted in LDS
 constexpr int kSortHalf = kSortCap / 2;
 
@@ -49,7 +52,8 @@ struct SliceParams {
 // Kernel stages that can be timed with HIP events (ksum_set_timing).
 enum StageId {
   ST_MISC = 0, ST_PROJECT, ST_SETUP, ST_NDFT_ADJOINT, ST_NDFT_FORWARD, ST_NFFT_SPREAD, ST_NFFT_GRID,
-  ST_NFFT_INTERP, ST_SORT_HIST, ST_SORT_SCAN, ST_SORT_SCATTER, ST_SORT_GROUP, ST_ACCUMULATE, ST_COUNT
+  ST_NFFT_INTERP, ST_SORT_HIST, ST_SORT_SCAN, ST_SORT_SCATTER, ST_SORT_GROUP, ST_ACCUMULATE,
+  ST_SORT_FALLBACK, ST_COUNT
 };
 
 struct Timer {
@@ -107,6 +111,8 @@ struct Layout {
   size_t off_wpart = 0;          // double[kWsumBlocks]
   size_t off_params = 0;         // SliceParams[B]
   size_t off_bounds = 0;         // uint32[B][2]
+  size_t off_counter = 0;        // uint32 tile queue of the projection
+  size_t off_bounds_part = 0;    // uint32[blocks][B][2] per-block min / max of the projection
   size_t off_z = 0;              // float[B][L]
   size_t off_t1 = 0;             // float[B][M]
   size_t off_t2 = 0;             // float[B][M]
@@ -123,6 +129,8 @@ struct Layout {
   size_t off_tot = 0;            // int64[B][2]      slice totals (A, S)
   size_t off_keys = 0;           // uint64[B][L] bucketed (key | index << 32)
   size_t off_keys2 = 0;          // uint64[B][L] scratch of the large-group sort
+  size_t off_desc = 0;           // int4[B][sort_groups] group descriptors
+  size_t off_fail = 0;           // uint32 count (+63 pad) and uint32[B][sort_groups] fallback list
   size_t total = 0;
 };
 
@@ -162,11 +170,13 @@ inline void mark(const ExecArgs &a, int stage) {
 
 hipError_t launch_weight_prep(const ExecArgs &a, const double *w64);
 hipError_t launch_projection(const ExecArgs &a);
+int projection_blocks(int64_t L, int nsl);
 hipError_t launch_slice_setup(const ExecArgs &a);
 hipError_t launch_ndft(const ExecArgs &a);
 hipError_t launch_nfft(const ExecArgs &a);
 hipError_t launch_sort_path(const ExecArgs &a);
 hipError_t launch_accumulate(const ExecArgs &a, float *s, bool first, bool last);
+hipError_t launch_nfft_interp(const ExecArgs &a, float *s, bool first, bool last);
 
 // host tables
 void generate_directions(int32_t d, int32_t P, uint64_t seed, double *out);

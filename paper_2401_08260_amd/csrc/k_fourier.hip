@@ -16,6 +16,8 @@
 // each lane accumulates into its own copy of that window in LDS ([cell][lane]
 // layout: conflict-free, deterministic), then lanes and chunks are reduced in a
 // fixed order.
+#include <algorithm>
+
 #include "device_common.h"
 #include "internal.h"
 
@@ -155,7 +157,6 @@ hipError_t launch_ndft(const ExecArgs &a) {
 // ---------------------------------------------------------------------------
 // NFFT
 // ---------------------------------------------------------------------------
-constexpr int kNfftPPL = 16;   // sources per lane in a spread block
 
 // Window weights of the 2 MW taps of a point with fractional offset x = fr - 1/2:
 // tap j and tap 2 MW - 1 - j are mirror images, poly_{2MW-1-j}(x) = poly_j(-x), so the
@@ -284,33 +285,73 @@ __global__ __launch_bounds__(256) void nfft_grid_kernel(FourierArgs a) {
   }
 }
 
+// Interpolation at the targets fused with the slice average (Algorithm
+// "Sliced Fast Fourier Summation", last step): every block owns a range of
+// targets, stages the grid windows of a sub-batch of slices in LDS and adds
+// t_{m,p} (plus the sorted part t2 of the Laplacian) over the slices in order in
+// FP64, so t never goes through HBM.  Optionally writes the per-slice t (probe).
+struct AccumArgs {
+  const float *t2;        // [nsl][M] sorted part (Laplacian) or null
+  double *sacc;           // [M] accumulator across batches
+  float *s;               // [M] output
+  float *t_out;           // [nsl][M] per-slice sums (probe) or null
+  int first, last;
+  double invP;
+  int tpt;                // targets per thread
+};
+
 template <int MW, int DEG>
-__global__ __launch_bounds__(256) void nfft_interp_kernel(FourierArgs a, int ychunk) {
-  extern __shared__ float G[];   // [W]
-  const int nyc = (int)((a.M + ychunk - 1) / ychunk);
-  const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * nyc);
+__global__ __launch_bounds__(256) void nfft_interp_accum_kernel(FourierArgs a, AccumArgs c, int sb) {
+  extern __shared__ float G[];   // [sb][W]
+  const int64_t per_block = 256 * (int64_t)c.tpt;
+  const int64_t nblk = (a.M + per_block - 1) / per_block;
+  const int64_t work = xcd_remap(blockIdx.x, nblk);
   if (work < 0) return;
-  const int p = (int)(work / nyc), c = (int)(work % nyc);
-  for (int i = threadIdx.x; i < a.W; i += blockDim.x) G[i] = a.gwin[(int64_t)p * a.W + i];
-  __syncthreads();
-  const SliceParams sp = a.params[p];
-  const float *Zy = a.Z + (int64_t)p * a.L;
-  float *tp = a.t + (int64_t)p * a.M;
+  const int64_t m0 = work * per_block;
   const float fn = (float)a.n;
-  const int64_t m0 = (int64_t)c * ychunk, m1 = min(a.M, m0 + ychunk);
-  for (int64_t m = m0 + threadIdx.x; m < m1; m += blockDim.x) {
-    const float yt = (Zy[m] - sp.fcmin) * sp.ftau + sp.shift;
-    const float u = yt * fn;
-    int i0 = (int)floorf(u);
-    const float fr = u - (float)i0;
-    i0 = min(max(i0, a.i0min), a.i0max);
-    float tap[2 * MW];
-    window_taps<MW, DEG>(a.poly, fr - 0.5f, tap);
-    const float *gb = G + (i0 - MW + 1 - a.lo);
-    float acc = 0.f;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int pb = 0; pb < a.nsl; pb += sb) {
+    const int np = min(sb, a.nsl - pb);
+    __syncthreads();
+    for (int i = threadIdx.x; i < np * a.W; i += blockDim.x) G[i] = a.gwin[(int64_t)pb * a.W + i];
+    __syncthreads();
+    for (int q = 0; q < np; ++q) {
+      const int p = pb + q;
+      const SliceParams sp = a.params[p];
+      const float *Zy = a.Z + (int64_t)p * a.L;
+      const float *Gp = G + q * a.W;
 #pragma unroll
-    for (int j = 0; j < 2 * MW; ++j) acc = fmaf(gb[j], tap[j], acc);
-    tp[m] = acc;
+      for (int k = 0; k < 4; ++k) {
+        if (k >= c.tpt) break;
+        const int64_t m = m0 + threadIdx.x + 256 * k;
+        if (m < a.M) {
+          const float yt = (Zy[m] - sp.fcmin) * sp.ftau + sp.shift;
+          const float u = yt * fn;
+          int i0 = (int)floorf(u);
+          const float fr = u - (float)i0;
+          i0 = min(max(i0, a.i0min), a.i0max);
+          float tap[2 * MW];
+          window_taps<MW, DEG>(a.poly, fr - 0.5f, tap);
+          const float *gb = Gp + (i0 - MW + 1 - a.lo);
+          float tv = 0.f;
+#pragma unroll
+          for (int j = 0; j < 2 * MW; ++j) tv = fmaf(gb[j], tap[j], tv);
+          if (c.t2) tv += c.t2[(int64_t)p * a.M + m];
+          if (c.t_out) c.t_out[(int64_t)p * a.M + m] = tv;
+          acc[k] += (double)tv;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k >= c.tpt) break;
+    const int64_t m = m0 + threadIdx.x + 256 * k;
+    if (m < a.M) {
+      const double v = (c.first ? 0.0 : c.sacc[m]) + acc[k];
+      if (c.last) c.s[m] = (float)(v * c.invP);
+      else c.sacc[m] = v;
+    }
   }
 }
 
@@ -329,11 +370,6 @@ static void launch_nfft_m(const FourierArgs &f, const ExecArgs &a) {
   nfft_spread_kernel<MW, DEG><<<gs, f.lanes, spread_lds, a.stream>>>(f);
   mark(a, ST_NFFT_GRID);
   nfft_grid_kernel<<<a.nsl, 256, grid_lds, a.stream>>>(f);
-  const int ychunk = 4096;
-  const int nyc = (int)((f.M + ychunk - 1) / ychunk);
-  mark(a, ST_NFFT_INTERP);
-  nfft_interp_kernel<MW, DEG><<<(unsigned)xcd_grid((int64_t)a.nsl * nyc), 256, (size_t)f.W * sizeof(float),
-                                a.stream>>>(f, ychunk);
 }
 
 int nfft_lanes_for(int W) {
@@ -343,7 +379,7 @@ int nfft_lanes_for(int W) {
   return lanes;
 }
 
-hipError_t launch_nfft(const ExecArgs &a) {
+static FourierArgs nfft_args(const ExecArgs &a) {
   const ksum_plan &pl = *a.plan;
   const Layout &lay = *a.lay;
   FourierArgs f{};
@@ -369,7 +405,12 @@ hipError_t launch_nfft(const ExecArgs &a) {
   f.i0max = lay.win_lo + lay.win_cells - 1 - m;
   f.twiddle = pl.d_twiddle;
   f.poly = pl.poly;
-  switch (m) {
+  return f;
+}
+
+hipError_t launch_nfft(const ExecArgs &a) {
+  const FourierArgs f = nfft_args(a);
+  switch (a.plan->params.window_m) {
     case 2: launch_nfft_m<2, 10>(f, a); break;
     case 3: launch_nfft_m<3, 10>(f, a); break;
     case 4: launch_nfft_m<4, 10>(f, a); break;
@@ -377,6 +418,41 @@ hipError_t launch_nfft(const ExecArgs &a) {
     case 6: launch_nfft_m<6, 10>(f, a); break;
     case 7: launch_nfft_m<7, 12>(f, a); break;
     case 8: launch_nfft_m<8, 12>(f, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int MW, int DEG>
+static void launch_interp_m(const FourierArgs &f, const AccumArgs &c, const ExecArgs &a) {
+  const int sb = std::max(1, std::min(f.nsl, (int)(32768 / (f.W * (int)sizeof(float)))));
+  const int64_t nblk = (f.M + 256 * (int64_t)c.tpt - 1) / (256 * (int64_t)c.tpt);
+  mark(a, ST_NFFT_INTERP);
+  nfft_interp_accum_kernel<MW, DEG><<<(unsigned)xcd_grid(nblk), 256, (size_t)sb * f.W * sizeof(float),
+                                      a.stream>>>(f, c, sb);
+}
+
+hipError_t launch_nfft_interp(const ExecArgs &a, float *s, bool first, bool last) {
+  const ksum_plan &pl = *a.plan;
+  const Layout &lay = *a.lay;
+  const FourierArgs f = nfft_args(a);
+  AccumArgs c{};
+  c.t2 = (pl.kernel == KSUM_LAPLACIAN) ? wsp<float>(a, lay.off_t2) : nullptr;
+  c.sacc = wsp<double>(a, lay.off_sacc);
+  c.s = s;
+  c.t_out = a.t_out ? a.t_out + (int64_t)a.p0 * lay.M : nullptr;
+  c.first = first ? 1 : 0;
+  c.last = last ? 1 : 0;
+  c.invP = 1.0 / (double)pl.P;
+  c.tpt = (int)std::max<int64_t>(1, std::min<int64_t>(4, lay.M / (256 * 1024)));
+  switch (pl.params.window_m) {
+    case 2: launch_interp_m<2, 10>(f, c, a); break;
+    case 3: launch_interp_m<3, 10>(f, c, a); break;
+    case 4: launch_interp_m<4, 10>(f, c, a); break;
+    case 5: launch_interp_m<5, 10>(f, c, a); break;
+    case 6: launch_interp_m<6, 10>(f, c, a); break;
+    case 7: launch_interp_m<7, 12>(f, c, a); break;
+    case 8: launch_interp_m<8, 12>(f, c, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -9,6 +9,8 @@
 // with k = 8 (l / 32) + s for step s = 0..7 of a K-block of 16 (any assignment of
 // the contraction index works as long as A and B agree), so a lane reads 8
 // consecutive floats of its row with two 16-byte LDS loads.
+#include <algorithm>
+
 #include "device_common.h"
 #include "internal.h"
 
@@ -21,34 +23,38 @@ constexpr int BN = 128;       // points
 constexpr int BK = kGemmBK;   // 16
 constexpr int LDA = BK + 4;   // padded LDS row (80 B): conflict-free 16-byte reads per 16 lanes
 
-template <typename InT>
+// Loads the BN x BK tile of union rows [l0, l0+BN) and columns [k0, k0+BK) into
+// registers, 2 groups of 4 consecutive columns per thread, VW elements per load
+// (VW = 4: 16-byte loads, d % 4 == 0; VW = 2: 8-byte loads, d even; VW = 1: any d).
+template <typename InT, int VW>
 struct PointLoader {
-  // Loads the BN x BK tile of union rows [l0, l0+BN) and columns [k0, k0+BK)
-  // into registers (2 groups of 4 consecutive columns per thread).
   const InT *x, *y;
   int64_t N, M, L;
   int d;
-  bool vec;   // d % 4 == 0 and FP32: one 16-byte load per group
 
   __device__ __forceinline__ void load(int64_t l0, int k0, float4 (&r)[2]) const {
     const int t = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const int e = t + i * 256;          // 512 groups of 4 columns
+      const int e = t + i * 256;
       const int row = e >> 2, k4 = (e & 3) * 4;
       const int64_t l = l0 + row;
       const int k = k0 + k4;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (l < L) {
         const InT *src = (l < M) ? (y + l * (int64_t)d) : (x + (l - M) * (int64_t)d);
-        if constexpr (sizeof(InT) == 4) {
-          if (vec) {
-            if (k < d) v = *reinterpret_cast<const float4 *>(src + k);
-          } else {
-            if (k + 0 < d) v.x = (float)src[k + 0];
-            if (k + 1 < d) v.y = (float)src[k + 1];
-            if (k + 2 < d) v.z = (float)src[k + 2];
-            if (k + 3 < d) v.w = (float)src[k + 3];
+        if constexpr (VW == 4) {
+          if (k < d) v = *reinterpret_cast<const float4 *>(src + k);
+        } else if constexpr (VW == 2) {
+          if (k < d) {
+            const float2 q = *reinterpret_cast<const float2 *>(src + k);
+            v.x = q.x;
+            v.y = q.y;
+          }
+          if (k + 2 < d) {
+            const float2 q = *reinterpret_cast<const float2 *>(src + k + 2);
+            v.z = q.x;
+            v.w = q.y;
           }
         } else {
           if (k + 0 < d) v.x = (float)src[k + 0];
@@ -62,155 +68,202 @@ struct PointLoader {
   }
 };
 
-template <typename InT>
-__global__ __launch_bounds__(256) void proj_gemm_kernel(const float *__restrict__ dirs, int d_pad,
-                                                       int p0, int nsl, PointLoader<InT> ld,
-                                                       float *__restrict__ Z, int64_t ldz,
-                                                       uint32_t *__restrict__ bounds,
-                                                       int n_col_tiles, int n_row_tiles) {
+struct GemmCtl {
+  const float *dirs;
+  int d_pad, p0, nsl;
+  float *Z;
+  int64_t ldz;
+  uint32_t *counter;      // tile queue head (zeroed before the launch)
+  uint32_t *part;         // [gridDim.x][nsl][2] per-block min / max keys
+  int n_col_tiles, n_row_tiles;
+};
+
+// Persistent blocks take (point tile, slice tile) work items from a device
+// counter in order, so neighbouring items (the slice tiles of one point tile)
+// run at the same time and every CU ends within about one tile of the others.
+// Per-slice min / max are kept in LDS and written once per block; the set-up
+// kernel reduces the blocks' partials (no global atomics on 2P addresses).
+template <typename InT, int VW>
+__global__ __launch_bounds__(256) void proj_gemm_kernel(GemmCtl g, PointLoader<InT, VW> ld) {
   __shared__ float As[2][BM * LDA];
   __shared__ float Bs[2][BN * LDA];
-
-  const int64_t work = xcd_remap(blockIdx.x, (int64_t)n_col_tiles * n_row_tiles);
-  if (work < 0) return;
-  // the row tiles of one point tile are consecutive work items (same XCD, X read once)
-  const int col_tile = (int)(work / n_row_tiles);
-  const int row_tile = (int)(work % n_row_tiles);
-  const int64_t l0 = (int64_t)col_tile * BN;
-  const int r0 = row_tile * BM;                 // local slice row of the tile
-  const float *A = dirs + (int64_t)(p0 + r0) * d_pad;
+  __shared__ uint32_t smin[kMaxBatch], smax[kMaxBatch];
+  __shared__ int s_tile;
 
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const int wm = wid >> 1, wn = wid & 1;
   const int lr = lane & 31, lh = lane >> 5;
-
-  f32x16 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-  auto load_a = [&](int k0, float4 (&r)[2]) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int e = t + i * 256;
-      const int row = e >> 2, k4 = (e & 3) * 4;
-      r[i] = *reinterpret_cast<const float4 *>(A + (int64_t)row * d_pad + k0 + k4);
-    }
-  };
-  auto store_tile = [&](float *S, const float4 (&r)[2]) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int e = t + i * 256;
-      const int row = e >> 2, k4 = (e & 3) * 4;
-      *reinterpret_cast<float4 *>(S + row * LDA + k4) = r[i];
-    }
-  };
-
-  float4 ra[2], rb[2];
-  load_a(0, ra);
-  ld.load(l0, 0, rb);
-  store_tile(As[0], ra);
-  store_tile(Bs[0], rb);
-  __syncthreads();
-
-  const int nk = d_pad / BK;
-  for (int kb = 0; kb < nk; ++kb) {
-    const int cur = kb & 1;
-    const bool more = kb + 1 < nk;
-    if (more) {
-      load_a((kb + 1) * BK, ra);
-      ld.load(l0, (kb + 1) * BK, rb);
-    }
-    float a[2][8], b[2][8];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const float *pa = As[cur] + (wm * 64 + i * 32 + lr) * LDA + lh * 8;
-      const float4 a0 = *reinterpret_cast<const float4 *>(pa);
-      const float4 a1 = *reinterpret_cast<const float4 *>(pa + 4);
-      a[i][0] = a0.x; a[i][1] = a0.y; a[i][2] = a0.z; a[i][3] = a0.w;
-      a[i][4] = a1.x; a[i][5] = a1.y; a[i][6] = a1.z; a[i][7] = a1.w;
-      const float *pb = Bs[cur] + (wn * 64 + i * 32 + lr) * LDA + lh * 8;
-      const float4 b0 = *reinterpret_cast<const float4 *>(pb);
-      const float4 b1 = *reinterpret_cast<const float4 *>(pb + 4);
-      b[i][0] = b0.x; b[i][1] = b0.y; b[i][2] = b0.z; b[i][3] = b0.w;
-      b[i][4] = b1.x; b[i][5] = b1.y; b[i][6] = b1.z; b[i][7] = b1.w;
-    }
-#pragma unroll
-    for (int s = 0; s < 8; ++s)
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
-    if (more) {
-      store_tile(As[cur ^ 1], ra);
-      store_tile(Bs[cur ^ 1], rb);
-    }
-    __syncthreads();
+  for (int i = t; i < g.nsl; i += 256) {
+    smin[i] = 0xffffffffu;
+    smax[i] = 0u;
   }
+  const int total = g.n_col_tiles * g.n_row_tiles;
+  const int nk = g.d_pad / BK;
 
-  // Epilogue: store Z (slice-major) and reduce per-slice min / max.
+  while (true) {
+    if (t == 0) s_tile = (int)atomicAdd(g.counter, 1u);
+    __syncthreads();
+    const int tile = s_tile;
+    if (tile >= total) break;
+    const int col_tile = tile / g.n_row_tiles;
+    const int row_tile = tile % g.n_row_tiles;
+    const int64_t l0 = (int64_t)col_tile * BN;
+    const int r0 = row_tile * BM;
+    const float *A = g.dirs + (int64_t)(g.p0 + r0) * g.d_pad;
+
+    f32x16 acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int row = r0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);   // local slice
-      float vmin = __builtin_huge_valf(), vmax = -__builtin_huge_valf();
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int64_t l = l0 + wn * 64 + j * 32 + lr;
-        const float v = acc[i][j][r];
-        if (row < nsl && l < ld.L) {
-          Z[(int64_t)row * ldz + l] = v;
-          vmin = fminf(vmin, v);
-          vmax = fmaxf(vmax, v);
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    auto load_a = [&](int k0, float4 (&r)[2]) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int e = t + i * 256;
+        const int row = e >> 2, k4 = (e & 3) * 4;
+        r[i] = *reinterpret_cast<const float4 *>(A + (int64_t)row * g.d_pad + k0 + k4);
+      }
+    };
+    auto store_tile = [&](float *S, const float4 (&r)[2]) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int e = t + i * 256;
+        const int row = e >> 2, k4 = (e & 3) * 4;
+        *reinterpret_cast<float4 *>(S + row * LDA + k4) = r[i];
+      }
+    };
+
+    float4 ra[2], rb[2];
+    load_a(0, ra);
+    ld.load(l0, 0, rb);
+    store_tile(As[0], ra);
+    store_tile(Bs[0], rb);
+    __syncthreads();
+
+    for (int kb = 0; kb < nk; ++kb) {
+      const int cur = kb & 1;
+      const bool more = kb + 1 < nk;
+      if (more) {
+        load_a((kb + 1) * BK, ra);
+        ld.load(l0, (kb + 1) * BK, rb);
+      }
+      const float *pa0 = As[cur] + (wm * 64 + lr) * LDA + lh * 8;
+      const float *pb0 = Bs[cur] + (wn * 64 + lr) * LDA + lh * 8;
+      const float4 alo0 = *reinterpret_cast<const float4 *>(pa0);
+      const float4 alo1 = *reinterpret_cast<const float4 *>(pa0 + 32 * LDA);
+      const float4 blo0 = *reinterpret_cast<const float4 *>(pb0);
+      const float4 blo1 = *reinterpret_cast<const float4 *>(pb0 + 32 * LDA);
+      const float4 ahi0 = *reinterpret_cast<const float4 *>(pa0 + 4);
+      const float4 ahi1 = *reinterpret_cast<const float4 *>(pa0 + 32 * LDA + 4);
+      const float4 bhi0 = *reinterpret_cast<const float4 *>(pb0 + 4);
+      const float4 bhi1 = *reinterpret_cast<const float4 *>(pb0 + 32 * LDA + 4);
+      const float al[2][4] = {{alo0.x, alo0.y, alo0.z, alo0.w}, {alo1.x, alo1.y, alo1.z, alo1.w}};
+      const float bl[2][4] = {{blo0.x, blo0.y, blo0.z, blo0.w}, {blo1.x, blo1.y, blo1.z, blo1.w}};
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(al[i][s], bl[j][s], acc[i][j], 0, 0, 0);
+      const float ah[2][4] = {{ahi0.x, ahi0.y, ahi0.z, ahi0.w}, {ahi1.x, ahi1.y, ahi1.z, ahi1.w}};
+      const float bh[2][4] = {{bhi0.x, bhi0.y, bhi0.z, bhi0.w}, {bhi1.x, bhi1.y, bhi1.z, bhi1.w}};
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ah[i][s], bh[j][s], acc[i][j], 0, 0, 0);
+      if (more) {
+        store_tile(As[cur ^ 1], ra);
+        store_tile(Bs[cur ^ 1], rb);
+      }
+      __syncthreads();
+    }
+
+    // Epilogue: store Z (slice-major) and fold the tile into the block's min / max.
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = r0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);   // local slice
+        float vmin = __builtin_huge_valf(), vmax = -__builtin_huge_valf();
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int64_t l = l0 + wn * 64 + j * 32 + lr;
+          const float v = acc[i][j][r];
+          if (row < g.nsl && l < ld.L) {
+            g.Z[(int64_t)row * g.ldz + l] = v;
+            vmin = fminf(vmin, v);
+            vmax = fmaxf(vmax, v);
+          }
+        }
+#pragma unroll
+        for (int off = 1; off < 32; off <<= 1) {
+          vmin = fminf(vmin, __shfl_xor(vmin, off, 64));
+          vmax = fmaxf(vmax, __shfl_xor(vmax, off, 64));
+        }
+        if (lr == 0 && row < g.nsl && vmin <= vmax) {
+          atomicMin(&smin[row], float_key(vmin));
+          atomicMax(&smax[row], float_key(vmax));
         }
       }
-#pragma unroll
-      for (int off = 1; off < 32; off <<= 1) {
-        vmin = fminf(vmin, __shfl_xor(vmin, off, 64));
-        vmax = fmaxf(vmax, __shfl_xor(vmax, off, 64));
-      }
-      if (lr == 0 && row < nsl && vmin <= vmax) {
-        atomicMin(bounds + 2 * row, float_key(vmin));
-        atomicMax(bounds + 2 * row + 1, float_key(vmax));
-      }
     }
+  }
+  __syncthreads();
+  uint32_t *out = g.part + (int64_t)blockIdx.x * g.nsl * 2;
+  for (int i = t; i < g.nsl; i += 256) {
+    out[2 * i] = smin[i];
+    out[2 * i + 1] = smax[i];
   }
 }
 
-__global__ void bounds_init_kernel(uint32_t *bounds, int nsl) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nsl) {
-    bounds[2 * i] = 0xffffffffu;
-    bounds[2 * i + 1] = 0u;
-  }
+__global__ void gemm_init_kernel(uint32_t *counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+}
+
+int projection_blocks(int64_t L, int nsl) {
+  const int64_t tiles = ((L + BN - 1) / BN) * (int64_t)((nsl + BM - 1) / BM);
+  return (int)std::min<int64_t>(tiles, 256 * kGemmBlocksPerCU);
 }
 
 hipError_t launch_projection(const ExecArgs &a) {
   const ksum_plan &pl = *a.plan;
   const Layout &lay = *a.lay;
-  uint32_t *bounds = wsp<uint32_t>(a, lay.off_bounds);
-  float *Z = wsp<float>(a, lay.off_z);
+  GemmCtl g;
+  g.dirs = pl.d_dirs;
+  g.d_pad = pl.d_pad;
+  g.p0 = a.p0;
+  g.nsl = a.nsl;
+  g.Z = wsp<float>(a, lay.off_z);
+  g.ldz = lay.L;
+  g.counter = wsp<uint32_t>(a, lay.off_counter);
+  g.part = wsp<uint32_t>(a, lay.off_bounds_part);
+  g.n_col_tiles = (int)((lay.L + BN - 1) / BN);
+  g.n_row_tiles = (a.nsl + BM - 1) / BM;
+  const unsigned grid = (unsigned)projection_blocks(lay.L, a.nsl);
   mark(a, ST_MISC);
-  bounds_init_kernel<<<(a.nsl + 255) / 256, 256, 0, a.stream>>>(bounds, a.nsl);
+  gemm_init_kernel<<<1, 64, 0, a.stream>>>(g.counter);
   mark(a, ST_PROJECT);
-  const int n_col = (int)((lay.L + BN - 1) / BN);
-  const int n_row = (a.nsl + BM - 1) / BM;
-  const int64_t grid = xcd_grid((int64_t)n_col * n_row);
-  const float *dirs = pl.d_dirs;
+  const int d = pl.d;
+  const bool al16 = ((uintptr_t)a.x % 16 == 0) && ((uintptr_t)a.y % 16 == 0);
+  const bool al8 = ((uintptr_t)a.x % 8 == 0) && ((uintptr_t)a.y % 8 == 0);
   if (a.f64in) {
-    PointLoader<double> ld{(const double *)a.x, (const double *)a.y, lay.N, lay.M, lay.L, pl.d, false};
-    proj_gemm_kernel<double><<<(unsigned)grid, 256, 0, a.stream>>>(dirs, pl.d_pad, a.p0, a.nsl, ld, Z,
-                                                                  lay.L, bounds, n_col, n_row);
+    PointLoader<double, 1> ld{(const double *)a.x, (const double *)a.y, lay.N, lay.M, lay.L, d};
+    proj_gemm_kernel<double, 1><<<grid, 256, 0, a.stream>>>(g, ld);
+  } else if (d % 4 == 0 && al16) {
+    PointLoader<float, 4> ld{(const float *)a.x, (const float *)a.y, lay.N, lay.M, lay.L, d};
+    proj_gemm_kernel<float, 4><<<grid, 256, 0, a.stream>>>(g, ld);
+  } else if (d % 2 == 0 && al8) {
+    PointLoader<float, 2> ld{(const float *)a.x, (const float *)a.y, lay.N, lay.M, lay.L, d};
+    proj_gemm_kernel<float, 2><<<grid, 256, 0, a.stream>>>(g, ld);
   } else {
-    const bool vec = (pl.d % 4 == 0) && ((uintptr_t)a.x % 16 == 0) && ((uintptr_t)a.y % 16 == 0);
-    PointLoader<float> ld{(const float *)a.x, (const float *)a.y, lay.N, lay.M, lay.L, pl.d, vec};
-    proj_gemm_kernel<float><<<(unsigned)grid, 256, 0, a.stream>>>(dirs, pl.d_pad, a.p0, a.nsl, ld, Z,
-                                                                 lay.L, bounds, n_col, n_row);
+    PointLoader<float, 1> ld{(const float *)a.x, (const float *)a.y, lay.N, lay.M, lay.L, d};
+    proj_gemm_kernel<float, 1><<<grid, 256, 0, a.stream>>>(g, ld);
   }
   return hipGetLastError();
 }

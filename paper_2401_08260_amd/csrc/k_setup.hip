@@ -25,7 +25,9 @@ struct SetupArgs {
   int32_t nb;             // buckets (sort path)
   int32_t lap_L;
   double T, sigma, eps, gauss_logc, cd;
-  const uint32_t *bounds;
+  uint32_t *bounds;       // [nsl][2] min / max keys (written here from the partials)
+  const uint32_t *part;   // [nparts][nsl][2] per-block partials of the projection, or null
+  int32_t nparts;
   const double *misc;     // misc[0] = sum |w|
   const float *deconv;    // [K+1]
   const double *costab;   // [lap_L]
@@ -57,6 +59,34 @@ __device__ double laplace_k1_series(double a, int d, double cd) {
 __global__ __launch_bounds__(256) void slice_setup_kernel(SetupArgs a) {
   const int p = blockIdx.x;
   __shared__ SliceParams sp;
+  __shared__ uint32_t red[8];
+  if (a.part) {
+    // min / max of the slice over the projection blocks' partials
+    uint32_t lo = 0xffffffffu, hi = 0u;
+    for (int b = threadIdx.x; b < a.nparts; b += blockDim.x) {
+      lo = min(lo, a.part[((int64_t)b * a.nsl + p) * 2]);
+      hi = max(hi, a.part[((int64_t)b * a.nsl + p) * 2 + 1]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      lo = min(lo, (uint32_t)__shfl_xor((int)lo, off, 64));
+      hi = max(hi, (uint32_t)__shfl_xor((int)hi, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red[threadIdx.x >> 6] = lo;
+      red[4 + (threadIdx.x >> 6)] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int nw = blockDim.x >> 6;
+      for (int w = 1; w < nw; ++w) {
+        red[0] = min(red[0], red[w]);
+        red[4] = max(red[4], red[4 + w]);
+      }
+      a.bounds[2 * p] = red[0];
+      a.bounds[2 * p + 1] = red[4];
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
     const float fmin = key_float(a.bounds[2 * p]);
     const float fmax = key_float(a.bounds[2 * p + 1]);
@@ -151,6 +181,8 @@ hipError_t launch_slice_setup(const ExecArgs &a) {
   s.gauss_logc = pl.gauss_logc;
   s.cd = pl.cd;
   s.bounds = wsp<uint32_t>(a, lay.off_bounds);
+  s.part = wsp<uint32_t>(a, lay.off_bounds_part);
+  s.nparts = projection_blocks(lay.L, a.nsl);
   s.misc = wsp<double>(a, lay.off_misc);
   s.deconv = pl.d_deconv;
   s.costab = pl.d_costab;

@@ -26,6 +26,8 @@
 //               global memory with the same ranking.
 // The order produced is the stable ascending order of the FP32 projections
 // (ties by union index), i.e. the permutation sigma of Sec. 3.2.
+#include <algorithm>
+
 #include "device_common.h"
 #include "internal.h"
 
@@ -48,6 +50,9 @@ struct SortArgs {
   float *t;             // [nsl][M]
   int32_t *perm;        // [nsl][L] (already offset to the batch) or null
   double cneg;          // c' (c_d, or alpha c_d for the Laplacian)
+  uint32_t *fail_count; // groups handed to the fallback kernel (zeroed by the scan kernel)
+  uint32_t *fail_list;  // [nsl * G] work items
+  int4 *desc;           // [nsl][G] (first bucket, first entry, end entry, 0) of each group
 };
 
 __device__ __forceinline__ int bucket_of(float z, float fcmin, float invw, int nb) {
@@ -146,7 +151,32 @@ __global__ __launch_bounds__(1024) void sort_scan_kernel(SortArgs a) {
     eAx += Av[q];
     eSx += Sv[q];
   }
+  // group descriptors: group g holds the buckets whose start offset lies in
+  // [g kSortHalf, (g + 1) kSortHalf); empty groups keep n = 0
+  __shared__ uint32_t sboff[2049];
+  int4 *desc = a.desc + (int64_t)p * a.G;
+  for (int g2 = threadIdx.x; g2 < a.G; g2 += blockDim.x) desc[g2] = make_int4(0, 0, 0, 0);
+  for (int q = 0; q < per; ++q) {
+    const int b = threadIdx.x * per + q;
+    if (b < a.nb) sboff[b] = boff[b];
+  }
+  if (threadIdx.x == 0) sboff[a.nb] = (uint32_t)a.L;
+  __syncthreads();
+  for (int q = 0; q < per; ++q) {
+    const int b = threadIdx.x * per + q;
+    if (b < a.nb) {
+      const uint32_t g2 = sboff[b] / kSortHalf;
+      const bool first = (b == 0) || (sboff[b - 1] / kSortHalf != g2);
+      const bool last = (b == a.nb - 1) || (sboff[b + 1] / kSortHalf != g2);
+      if (first) {
+        desc[g2].x = b;                  // first bucket
+        desc[g2].y = (int)sboff[b];      // first entry
+      }
+      if (last) desc[g2].z = (int)sboff[b + 1];   // end entry
+    }
+  }
   if (threadIdx.x == 0) {
+    if (p == 0) *a.fail_count = 0u;
     boff[a.nb] = (uint32_t)a.L;
     a.tot[2 * p] = tA;
     a.tot[2 * p + 1] = tS;
@@ -154,26 +184,89 @@ __global__ __launch_bounds__(1024) void sort_scan_kernel(SortArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// S3: scatter (key, union index) into buckets
+// S3: scatter (key, union index) into buckets.  Each tile of kScatTile entries is
+// first ordered by bucket in LDS, so the global writes come as runs of
+// consecutive positions per bucket instead of isolated 8-byte stores.
 // ---------------------------------------------------------------------------
+constexpr int kScatTile = 4096;
+
 __global__ __launch_bounds__(512) void sort_scatter_kernel(SortArgs a) {
-  __shared__ uint32_t cur[2048];
+  __shared__ unsigned long long tk[kScatTile];
+  __shared__ uint16_t tb[kScatTile];
+  __shared__ uint32_t cursor[2048], tcnt[2048], tstart[2048];
+  __shared__ long long sm[64];
   const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * kSortChunks);
   if (work < 0) return;
   const int p = (int)(work / kSortChunks), c = (int)(work % kSortChunks);
   const int64_t base = ((int64_t)p * kSortChunks + c) * a.nb;
-  for (int b = threadIdx.x; b < a.nb; b += blockDim.x) cur[b] = a.hcnt[base + b];
-  __syncthreads();
+  for (int b = threadIdx.x; b < a.nb; b += blockDim.x) cursor[b] = a.hcnt[base + b];
   const SliceParams sp = a.params[p];
   const int64_t chunk = (a.L + kSortChunks - 1) / kSortChunks;
   const int64_t l0 = c * chunk, l1 = min(a.L, l0 + chunk);
   const float *Zp = a.Z + (int64_t)p * a.L;
   unsigned long long *kp = a.keys + (int64_t)p * a.L;
-  for (int64_t l = l0 + threadIdx.x; l < l1; l += blockDim.x) {
-    const float z = Zp[l];
-    const int b = bucket_of(z, sp.fcmin, sp.inv_width, a.nb);
-    const uint32_t pos = atomicAdd(&cur[b], 1u);
-    kp[pos] = (unsigned long long)float_key(z) | ((unsigned long long)(uint32_t)l << 32);
+  const int per = (a.nb + 511) / 512;    // buckets per thread in the scan (<= 4)
+  for (int64_t t0 = l0; t0 < l1; t0 += kScatTile) {
+    const int tn = (int)min((int64_t)kScatTile, l1 - t0);
+    for (int b = threadIdx.x; b < a.nb; b += blockDim.x) tcnt[b] = 0;
+    __syncthreads();
+    // bucket of every entry of the tile; ranks within its bucket
+    int bk[kScatTile / 512];
+    uint32_t rk[kScatTile / 512];
+#pragma unroll
+    for (int q = 0; q < kScatTile / 512; ++q) {
+      const int i = threadIdx.x + q * 512;
+      if (i < tn) {
+        const float z = Zp[t0 + i];
+        const int b = bucket_of(z, sp.fcmin, sp.inv_width, a.nb);
+        bk[q] = b;
+        rk[q] = atomicAdd(&tcnt[b], 1u);
+        tk[i] = (unsigned long long)float_key(z) | ((unsigned long long)(uint32_t)(t0 + i) << 32);
+      }
+    }
+    __syncthreads();
+    // exclusive scan of the tile's bucket counts
+    long long loc = 0;
+    for (int q = 0; q < per; ++q) {
+      const int b = threadIdx.x * per + q;
+      if (b < a.nb) loc += tcnt[b];
+    }
+    long long tot;
+    long long ex = block_exclusive_scan(loc, sm, &tot);
+    for (int q = 0; q < per; ++q) {
+      const int b = threadIdx.x * per + q;
+      if (b < a.nb) {
+        tstart[b] = (uint32_t)ex;
+        ex += tcnt[b];
+      }
+    }
+    __syncthreads();
+    // reorder the tile by bucket in LDS (entries of one bucket stay in tile order)
+    unsigned long long mine[kScatTile / 512];
+#pragma unroll
+    for (int q = 0; q < kScatTile / 512; ++q) {
+      const int i = threadIdx.x + q * 512;
+      if (i < tn) mine[q] = tk[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kScatTile / 512; ++q) {
+      const int i = threadIdx.x + q * 512;
+      if (i < tn) {
+        const uint32_t pos = tstart[bk[q]] + rk[q];
+        tk[pos] = mine[q];
+        tb[pos] = (uint16_t)bk[q];
+      }
+    }
+    __syncthreads();
+    // consecutive LDS entries -> consecutive global positions within a bucket
+    for (int i = threadIdx.x; i < tn; i += blockDim.x) {
+      const int b = tb[i];
+      kp[cursor[b] + (uint32_t)i - tstart[b]] = tk[i];
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < a.nb; b += blockDim.x) cursor[b] += tcnt[b];
+    __syncthreads();
   }
 }
 
@@ -187,6 +280,10 @@ struct RankState {
   long long sm[64];
   uint32_t flag;
 };
+
+constexpr int kSortCapPad = kSortCap + kSortCap / 16;   // padded LDS arrays (pad16)
+constexpr int kNS = 2048;            // value-linear sub-buckets of a group sorted in LDS
+constexpr int kSubRunMax = 64;       // longest sub-bucket run sorted by insertion
 
 // Ranks entries [0, n) of (kin, iin) by digit(d) and returns, in pos[r] for the
 // entries this thread owns (position (wid * kR + r) * 64 + lane), their offset
@@ -301,13 +398,22 @@ __device__ __forceinline__ void block_minmax(const uint32_t *v, int n, uint32_t 
   __syncthreads();
 }
 
+// LDS index of entry i in a padded array: one spare word after every 16 entries,
+// so 16 consecutive entries per thread sit at a stride of 17 words across lanes.
+__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
+__device__ __forceinline__ int nopad(int i) { return i; }
+
 // Fixed-point prefix scan over the sorted tile [0, n) with carry-in (cA, cS);
-// emits t at the targets and the permutation.  Returns the tile totals.
+// emits t at the targets and the permutation; adds the tile totals to (cA, cS).
+// Thread t owns the 16 consecutive entries [16t, 16t+16): a serial prefix in
+// registers plus one block scan of the per-thread totals.  IX maps an entry to
+// its LDS index (padded arrays avoid bank conflicts).
+template <int (*IX)(int)>
 __device__ __forceinline__ void scan_emit(const SortArgs &a, int p, const SliceParams &sp, int eA,
-                                          const uint32_t *K, const uint32_t *I, int n, int64_t out_pos,
-                                          long long &cA, long long &cS, long long Atot, long long Stot,
-                                          long long *sm) {
-  const int per = kSortCap / 256;   // 16 consecutive entries per thread
+                                          const uint32_t *K, const uint32_t *I, const float *W, int n,
+                                          int64_t out_pos, long long &cA, long long &cS, long long Atot,
+                                          long long Stot, long long *sm) {
+  constexpr int per = kSortCap / 256;   // 16 consecutive entries per thread
   const int i0 = threadIdx.x * per;
   long long fa[per], fs[per];
   long long lA = 0, lS = 0;
@@ -317,12 +423,11 @@ __device__ __forceinline__ void scan_emit(const SortArgs &a, int p, const SliceP
     fa[q] = 0;
     fs[q] = 0;
     if (i < n) {
-      const uint32_t idx = I[i];
+      const uint32_t idx = I[IX(i)];
       if ((int64_t)idx >= a.M) {
-        const float v = a.w[idx - a.M];
-        const float z = key_float(K[i]);
+        const float v = W ? W[IX(i)] : a.w[idx - a.M];
         fa[q] = fix_a(v, eA);
-        fs[q] = fix_s(v, z, sp.cmid, sp.eS);
+        fs[q] = fix_s(v, key_float(K[IX(i)]), sp.cmid, sp.eS);
       }
     }
     lA += fa[q];
@@ -337,13 +442,12 @@ __device__ __forceinline__ void scan_emit(const SortArgs &a, int p, const SliceP
   for (int q = 0; q < per; ++q) {
     const int i = i0 + q;
     if (i < n) {
-      const uint32_t idx = I[i];
+      const uint32_t idx = I[IX(i)];
       if ((int64_t)idx < a.M) {
-        const double zb = (double)key_float(K[i]) - sp.cmid;
+        const double zb = (double)key_float(K[IX(i)]) - sp.cmid;
         const long long dA = 2 * exA - Atot;
         const long long dS = 2 * exS - Stot;
-        const double tv = -a.cneg * (zb * ((double)dA * sa) - (double)dS * ss);
-        tp[idx] = (float)tv;
+        tp[idx] = (float)(-a.cneg * (zb * ((double)dA * sa) - (double)dS * ss));
       }
       if (a.perm) a.perm[(int64_t)p * a.L + out_pos + i] = (int32_t)idx;
     }
@@ -383,15 +487,6 @@ __device__ __forceinline__ bool fix_ties(uint32_t *K, uint32_t *I, int n, uint32
   const bool ok = (*flag == 0);
   __syncthreads();
   return ok;
-}
-
-__device__ __forceinline__ int lower_bound_u32(const uint32_t *arr, int n, uint32_t v) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (arr[mid] < v) lo = mid + 1; else hi = mid;
-  }
-  return lo;
 }
 
 // Streaming stable LSD pass over a segment of global memory (one workgroup).
@@ -442,18 +537,31 @@ __device__ void stream_pass(GroupShared &g, const unsigned long long *src, unsig
   }
 }
 
-__global__ __launch_bounds__(256) void sort_group_kernel(SortArgs a) {
-  __shared__ GroupShared g;
-  const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * a.G);
-  if (work < 0) return;
-  const int p = (int)(work / a.G), grp = (int)(work % a.G);
-  const uint32_t *boff = a.boff + (int64_t)p * (a.nb + 1);
-  const int b_lo = lower_bound_u32(boff, a.nb, (uint32_t)grp * kSortHalf);
-  const int b_hi = lower_bound_u32(boff, a.nb, (uint32_t)(grp + 1) * kSortHalf);
-  if (b_lo >= b_hi) return;
-  const int64_t e_lo = boff[b_lo];
-  const int64_t e_hi = (b_hi < a.nb) ? (int64_t)boff[b_hi] : a.L;
-  const int64_t n = e_hi - e_lo;
+// Locates work item (slice, group): the buckets b whose start offset lies in
+// [group * kSortHalf, (group + 1) * kSortHalf), i.e. whole consecutive buckets.
+struct GroupDesc {
+  int p, b_lo;
+  int64_t e_lo;
+  int n;
+};
+
+__device__ __forceinline__ GroupDesc group_desc(const SortArgs &a, int64_t item) {
+  const int4 v = a.desc[item];
+  GroupDesc d;
+  d.p = (int)(item / a.G);
+  d.b_lo = v.x;
+  d.e_lo = v.y;
+  d.n = v.z - v.y;
+  return d;
+}
+
+// Radix / streaming sort of one group the fast kernel handed over.
+__device__ void fallback_group(const SortArgs &a, GroupShared &g, int64_t item) {
+  const GroupDesc dsc = group_desc(a, item);
+  const int p = dsc.p;
+  const int b_lo = dsc.b_lo;
+  const int64_t e_lo = dsc.e_lo;
+  const int64_t n = dsc.n;
   if (n <= 0) return;
   const SliceParams sp = a.params[p];
   const int eA = (int)a.misc[1];
@@ -492,7 +600,7 @@ __global__ __launch_bounds__(256) void sort_group_kernel(SortArgs a) {
         cur ^= 1;
       }
     }
-    scan_emit(a, p, sp, eA, g.K[cur], g.I[cur], nn, e_lo, cA, cS, Atot, Stot, g.rs.sm);
+    scan_emit<nopad>(a, p, sp, eA, g.K[cur], g.I[cur], nullptr, nn, e_lo, cA, cS, Atot, Stot, g.rs.sm);
     return;
   }
 
@@ -546,7 +654,257 @@ __global__ __launch_bounds__(256) void sort_group_kernel(SortArgs a) {
       g.I[0][i] = (uint32_t)(e >> 32);
     }
     __syncthreads();
-    scan_emit(a, p, sp, eA, g.K[0], g.I[0], tn, e_lo + t0, cA, cS, Atot, Stot, g.rs.sm);
+    scan_emit<nopad>(a, p, sp, eA, g.K[0], g.I[0], nullptr, tn, e_lo + t0, cA, cS, Atot, Stot, g.rs.sm);
+    __syncthreads();
+  }
+}
+
+
+__global__ __launch_bounds__(256) void sort_fallback_kernel(SortArgs a) {
+  __shared__ GroupShared g;
+  const uint32_t count = *a.fail_count;
+  for (uint32_t j = blockIdx.x; j < count; j += gridDim.x) {
+    fallback_group(a, g, a.fail_list[j]);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// S4 fast path.  A group (<= kSortCap entries) is sorted by (key, index) with
+// one counting pass into kNS value-linear sub-buckets over [min, max] of the
+// group (a monotone map); inside a sub-bucket every entry counts the entries
+// smaller than itself and moves to that rank.  The keys stay in registers until
+// they are scattered into sub-bucket order in LDS, the weights are gathered up
+// front and carried along, and the next group's keys are loaded while the
+// current group is processed.  Groups that are too large, have all keys equal
+// or a sub-bucket longer than kSubRunMax go to the fallback list.
+// 512 threads, kFPer = 8 consecutive entries per thread in the scan.
+// ---------------------------------------------------------------------------
+constexpr int kFThreads = 512;
+constexpr int kFPer = kSortCap / kFThreads;          // 8
+constexpr int kFWaves = kFThreads / 64;
+constexpr int kFCapPad = kSortCap + kSortCap / 8;    // pad8 layout
+
+// one spare word per 8 entries (stride 9 words between threads' 8-entry blocks)
+__device__ __forceinline__ int pad8(int i) { return i + (i >> 3); }
+// one spare word per 4 counters (stride 5 words between threads' 4-counter blocks)
+__device__ __forceinline__ int pad4(int i) { return i + (i >> 2); }
+
+struct FastShared {
+  uint32_t K[kFCapPad];
+  uint32_t I[kFCapPad];
+  float W[kFCapPad];
+  uint16_t inv[kFCapPad];      // sorted position -> entry (pad8 layout)
+  uint32_t cnt[kNS + kNS / 4];
+  double sm[64];
+  uint32_t red[2 * kFWaves];
+  uint32_t flag;
+};
+
+__device__ __forceinline__ void load_group_keys(const SortArgs &a, const GroupDesc &d,
+                                                unsigned long long (&kr)[kFPer]) {
+  const unsigned long long *seg = a.keys + (int64_t)d.p * a.L + d.e_lo;
+#pragma unroll
+  for (int q = 0; q < kFPer; ++q) {
+    const int i = threadIdx.x + kFThreads * q;
+    kr[q] = (d.n <= kSortCap && i < d.n) ? seg[i] : ~0ull;
+  }
+}
+
+__device__ __forceinline__ void push_fallback(const SortArgs &a, int64_t item) {
+  if (threadIdx.x == 0) a.fail_list[atomicAdd(a.fail_count, 1u)] = (uint32_t)item;
+}
+
+__device__ __forceinline__ int sub_bucket(uint32_t key, float zlo, float inv) {
+  const float q = (key_float(key) - zlo) * inv;
+  return (q < (float)kNS) ? (int)q : kNS - 1;
+}
+
+// Scan of a sorted group: FP64 prefix sums inside the group, taken in its
+// canonical (key, index) order (so the rounding is the same on every run), on
+// top of the exact fixed-point prefix of the group's first bucket.  W holds the
+// weights of the sources (0 for targets).  Thread t owns entries [8t, 8t+8).
+__device__ __forceinline__ void scan_emit_fast(const SortArgs &a, int p, const SliceParams &sp, int eA,
+                                               const FastShared &f, int n, int64_t out_pos, long long preA,
+                                               long long preS, long long totA, long long totS, double *smd) {
+  const int i0 = threadIdx.x * kFPer;
+  const double sa = ldexp(1.0, -eA), ss = ldexp(1.0, -sp.eS);
+  uint32_t kk[kFPer], ii[kFPer];
+  float ww[kFPer];
+  double lA = 0.0, lS = 0.0;
+#pragma unroll
+  for (int q = 0; q < kFPer; ++q) {
+    const int j = i0 + q;
+    kk[q] = 0;
+    ii[q] = 0;
+    ww[q] = 0.f;
+    if (j < n) {
+      const int e = pad8(f.inv[pad8(j)]);
+      kk[q] = f.K[e];
+      ii[q] = f.I[e];
+      ww[q] = f.W[e];
+      lA += (double)ww[q];
+      lS += (double)ww[q] * ((double)key_float(kk[q]) - sp.cmid);
+    }
+  }
+  double tA, tS;
+  double exA = block_exclusive_scan(lA, smd, &tA) + (double)preA * sa;
+  double exS = block_exclusive_scan(lS, smd, &tS) + (double)preS * ss;
+  const double totAd = (double)totA * sa, totSd = (double)totS * ss;
+  float *tp = a.t + (int64_t)p * a.M;
+#pragma unroll
+  for (int q = 0; q < kFPer; ++q) {
+    const int j = i0 + q;
+    if (j < n) {
+      const double zb = (double)key_float(kk[q]) - sp.cmid;
+      if ((int64_t)ii[q] < a.M)
+        tp[ii[q]] = (float)(-a.cneg * (zb * (2.0 * exA - totAd) - (2.0 * exS - totSd)));
+      if (a.perm) a.perm[(int64_t)p * a.L + out_pos + j] = (int32_t)ii[q];
+      exA += (double)ww[q];
+      exS += (double)ww[q] * zb;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
+  __shared__ FastShared f;
+  const int64_t total = (int64_t)a.nsl * a.G;
+  // XCD-contiguous ranges of work items; the blocks of an XCD stride through it
+  const int x = blockIdx.x & 7, r = blockIdx.x >> 3, gx = gridDim.x >> 3;
+  const int64_t per_x = (total + 7) / 8;
+  const int64_t lo = x * per_x, hi = min(total, lo + per_x);
+  int64_t item = lo + r;
+  GroupDesc nd{};
+  unsigned long long nk[kFPer];
+  if (item < hi) {
+    nd = group_desc(a, item);
+    load_group_keys(a, nd, nk);
+  }
+  const int eA = (int)a.misc[1];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  while (item < hi) {
+    const GroupDesc d = nd;
+    unsigned long long kc[kFPer];
+#pragma unroll
+    for (int q = 0; q < kFPer; ++q) kc[q] = nk[q];
+    const int64_t next = item + gx;
+    if (next < hi) {
+      nd = group_desc(a, next);
+      load_group_keys(a, nd, nk);
+    }
+    const int64_t cur_item = item;
+    item = next;
+    if (d.n <= 0) continue;
+    if (d.n > kSortCap) {
+      push_fallback(a, cur_item);
+      continue;
+    }
+    const int n = d.n, p = d.p;
+    // weights of the sources, gathered now and used at the scatter
+    float wv[kFPer];
+#pragma unroll
+    for (int q = 0; q < kFPer; ++q) {
+      const uint32_t idx = (uint32_t)(kc[q] >> 32);
+      wv[q] = (threadIdx.x + kFThreads * q < n && (int64_t)idx >= a.M) ? a.w[idx - a.M] : 0.f;
+    }
+    // key range of the group
+    uint32_t kmin = 0xffffffffu, kmax = 0u;
+#pragma unroll
+    for (int q = 0; q < kFPer; ++q) {
+      if (threadIdx.x + kFThreads * q < n) {
+        kmin = min(kmin, (uint32_t)kc[q]);
+        kmax = max(kmax, (uint32_t)kc[q]);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off, 64));
+      kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off, 64));
+    }
+    if (lane == 0) {
+      f.red[wid] = kmin;
+      f.red[kFWaves + wid] = kmax;
+    }
+    for (int i = threadIdx.x; i < kNS + kNS / 4; i += kFThreads) f.cnt[i] = 0;
+    if (threadIdx.x == 0) f.flag = 0;
+    __syncthreads();
+    kmin = f.red[0];
+    kmax = f.red[kFWaves];
+    for (int w2 = 1; w2 < kFWaves; ++w2) {
+      kmin = min(kmin, f.red[w2]);
+      kmax = max(kmax, f.red[kFWaves + w2]);
+    }
+    const float zlo = key_float(kmin), zhi = key_float(kmax);
+    const double inv_d = (double)kNS / ((double)zhi - (double)zlo);
+    if (kmin == kmax || !(inv_d < 1e30)) {
+      __syncthreads();
+      push_fallback(a, cur_item);
+      continue;
+    }
+    const float inv = (float)inv_d;
+#pragma unroll
+    for (int q = 0; q < kFPer; ++q)
+      if (threadIdx.x + kFThreads * q < n) atomicAdd(&f.cnt[pad4(sub_bucket((uint32_t)kc[q], zlo, inv))], 1u);
+    __syncthreads();
+    {
+      // exclusive scan of the counters, 4 consecutive per thread (stride 5 words)
+      constexpr int per = kNS / kFThreads;
+      uint32_t loc[per];
+      double sum = 0.0;
+#pragma unroll
+      for (int q = 0; q < per; ++q) {
+        loc[q] = f.cnt[pad4(threadIdx.x * per + q)];
+        sum += (double)loc[q];
+      }
+      double tot;
+      uint32_t ex = (uint32_t)block_exclusive_scan(sum, f.sm, &tot);
+#pragma unroll
+      for (int q = 0; q < per; ++q) {
+        f.cnt[pad4(threadIdx.x * per + q)] = ex;
+        ex += loc[q];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kFPer; ++q) {
+      if (threadIdx.x + kFThreads * q < n) {
+        const int pos = pad8((int)atomicAdd(&f.cnt[pad4(sub_bucket((uint32_t)kc[q], zlo, inv))], 1u));
+        f.K[pos] = (uint32_t)kc[q];
+        f.I[pos] = (uint32_t)(kc[q] >> 32);
+        f.W[pos] = wv[q];
+      }
+    }
+    __syncthreads();
+    // cnt[sb] is now the end of sub-bucket sb.  Rank every entry inside its run by
+    // (key, index) -- independent LDS reads, no serial chain -- and record which
+    // entry lands at each sorted position.
+#pragma unroll
+    for (int q = 0; q < kFPer; ++q) {
+      const int i = threadIdx.x + kFThreads * q;
+      if (i < n) {
+        const uint32_t kk = f.K[pad8(i)], ii = f.I[pad8(i)];
+        const int sb = sub_bucket(kk, zlo, inv);
+        const int e = (int)f.cnt[pad4(sb)];
+        const int b = sb ? (int)f.cnt[pad4(sb - 1)] : 0;
+        int rank = 0;
+        if (e - b > kSubRunMax) {
+          f.flag = 1;
+        } else {
+          const unsigned long long v = ((unsigned long long)kk << 32) | ii;
+          for (int j = b; j < e; ++j)
+            rank += ((((unsigned long long)f.K[pad8(j)] << 32) | f.I[pad8(j)]) < v) ? 1 : 0;
+        }
+        f.inv[pad8(min(b + rank, kSortCap - 1))] = (uint16_t)i;
+      }
+    }
+    __syncthreads();
+    if (f.flag) {
+      __syncthreads();
+      push_fallback(a, cur_item);
+      continue;
+    }
+    const SliceParams sp = a.params[p];
+    scan_emit_fast(a, p, sp, eA, f, n, d.e_lo, a.bpre[2 * ((int64_t)p * a.nb + d.b_lo)],
+                   a.bpre[2 * ((int64_t)p * a.nb + d.b_lo) + 1], a.tot[2 * p], a.tot[2 * p + 1], f.sm);
     __syncthreads();
   }
 }
@@ -571,6 +929,9 @@ hipError_t launch_sort_path(const ExecArgs &a) {
   s.tot = wsp<long long>(a, lay.off_tot);
   s.keys = wsp<unsigned long long>(a, lay.off_keys);
   s.keys2 = wsp<unsigned long long>(a, lay.off_keys2);
+  s.fail_count = wsp<uint32_t>(a, lay.off_fail);
+  s.fail_list = wsp<uint32_t>(a, lay.off_fail) + 64;
+  s.desc = wsp<int4>(a, lay.off_desc);
   s.t = wsp<float>(a, pl.kernel == KSUM_LAPLACIAN ? lay.off_t2 : lay.off_t1);
   s.perm = a.perm_out ? a.perm_out + (int64_t)a.p0 * lay.L : nullptr;
   s.cneg = pl.sort_const;
@@ -581,9 +942,12 @@ hipError_t launch_sort_path(const ExecArgs &a) {
   sort_scan_kernel<<<a.nsl, 1024, 0, a.stream>>>(s);
   mark(a, ST_SORT_SCATTER);
   sort_scatter_kernel<<<g1, 512, 0, a.stream>>>(s);
-  const unsigned g4 = (unsigned)xcd_grid((int64_t)a.nsl * lay.sort_groups);
+  const int64_t items = (int64_t)a.nsl * lay.sort_groups;
+  const unsigned g4 = (unsigned)std::min<int64_t>(xcd_grid(items), 256 * 2);
   mark(a, ST_SORT_GROUP);
-  sort_group_kernel<<<g4, 256, 0, a.stream>>>(s);
+  sort_fast_kernel<<<g4, kFThreads, 0, a.stream>>>(s);
+  mark(a, ST_SORT_FALLBACK);
+  sort_fallback_kernel<<<256, 256, 0, a.stream>>>(s);
   return hipGetLastError();
 }
 

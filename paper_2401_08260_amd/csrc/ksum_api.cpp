@@ -103,6 +103,7 @@ Layout make_layout(const ksum_plan &pl, int64_t N, int64_t M) {
   y.M = M;
   y.L = N + M;
   y.B = pl.params.slice_batch > 0 ? std::min(pl.params.slice_batch, pl.P) : pl.P;
+  y.B = std::min(y.B, kMaxBatch);
   const int64_t B = y.B;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -114,8 +115,14 @@ Layout make_layout(const ksum_plan &pl, int64_t N, int64_t M) {
   y.off_wpart = take(kWsumBlocks * sizeof(double));
   y.off_params = take(B * sizeof(SliceParams));
   y.off_bounds = take(B * 2 * sizeof(uint32_t));
+  y.off_counter = take(64);
+  y.off_bounds_part = take((size_t)projection_blocks(y.L, (int)B) * B * 2 * sizeof(uint32_t));
   y.off_z = take((size_t)B * y.L * sizeof(float));
-  y.off_t1 = take((size_t)B * M * sizeof(float));
+  // per-slice sums that pass through HBM: NDFT output and the negative-distance sort
+  // output (t1), the Laplacian's sorted part (t2); the NFFT interpolation adds its
+  // part directly into the slice average
+  const bool need_t1 = (pl.kernel == KSUM_NEGDIST) || (pl.use_fourier && pl.method == KSUM_1D_NDFT);
+  y.off_t1 = need_t1 ? take((size_t)B * M * sizeof(float)) : 0;
   y.off_t2 = (pl.kernel == KSUM_LAPLACIAN) ? take((size_t)B * M * sizeof(float)) : y.off_t1;
   y.off_sacc = take((size_t)M * sizeof(double));
   y.off_wf = take((size_t)N * sizeof(float));
@@ -127,7 +134,7 @@ Layout make_layout(const ksum_plan &pl, int64_t N, int64_t M) {
     } else {
       nfft_window(pl.n_grid, pl.params.T, pl.params.window_m, &y.win_lo, &y.win_cells);
       const int lanes = nfft_lanes_for(y.win_cells);
-      y.nfft_chunks = (int32_t)((N + (int64_t)lanes * 16 - 1) / ((int64_t)lanes * 16));
+      y.nfft_chunks = (int32_t)((N + (int64_t)lanes * kNfftPPL - 1) / ((int64_t)lanes * kNfftPPL));
       y.off_fpart = take((size_t)B * y.nfft_chunks * y.win_cells * sizeof(float));
       y.off_grid = take((size_t)B * y.win_cells * sizeof(float));
     }
@@ -135,7 +142,7 @@ Layout make_layout(const ksum_plan &pl, int64_t N, int64_t M) {
   }
   if (pl.use_sort) {
     const int64_t L = y.L;
-    y.nb = (int32_t)std::min<int64_t>(2048, std::max<int64_t>(64, next_pow2((L + 127) / 128)));
+    y.nb = (int32_t)std::min<int64_t>(2048, std::max<int64_t>(64, next_pow2((L + 511) / 512)));
     y.sort_groups = (int32_t)((L + kSortHalf - 1) / kSortHalf + 1);
     y.off_hcnt = take((size_t)B * kSortChunks * y.nb * sizeof(uint32_t));
     y.off_hsum = take((size_t)B * kSortChunks * y.nb * 2 * sizeof(long long));
@@ -144,6 +151,8 @@ Layout make_layout(const ksum_plan &pl, int64_t N, int64_t M) {
     y.off_tot = take((size_t)B * 2 * sizeof(long long));
     y.off_keys = take((size_t)B * L * sizeof(unsigned long long));
     y.off_keys2 = take((size_t)B * L * sizeof(unsigned long long));
+    y.off_desc = take((size_t)B * y.sort_groups * sizeof(int4));
+    y.off_fail = take((64 + (size_t)B * y.sort_groups) * sizeof(uint32_t));
   }
   y.total = o;
   return y;
@@ -413,7 +422,10 @@ static ksum_status execute_impl(ksum_plan *plan, const void *x, int64_t N, const
     if (e == hipSuccess && plan->use_fourier)
       e = (plan->method == KSUM_1D_NDFT) ? launch_ndft(a) : launch_nfft(a);
     if (e == hipSuccess && plan->use_sort) e = launch_sort_path(a);
-    if (e == hipSuccess) e = launch_accumulate(a, s, p0 == 0, p0 + a.nsl >= plan->P);
+    const bool first = p0 == 0, last = p0 + a.nsl >= plan->P;
+    if (e == hipSuccess)
+      e = (plan->use_fourier && plan->method == KSUM_1D_NFFT) ? launch_nfft_interp(a, s, first, last)
+                                                              : launch_accumulate(a, s, first, last);
   }
   mark(a, -1);
   if (prev != plan->params.device) (void)hipSetDevice(prev);
@@ -439,7 +451,7 @@ ksum_status ksum_execute_probe(ksum_plan *plan, const float *x, int64_t N, const
 
 static const char *kStageNames[ST_COUNT] = {
     "misc", "project", "setup", "ndft_adjoint", "ndft_forward", "nfft_spread", "nfft_grid",
-    "nfft_interp", "sort_hist", "sort_scan", "sort_scatter", "sort_group", "accumulate"};
+    "nfft_interp", "sort_hist", "sort_scan", "sort_scatter", "sort_group", "accumulate", "sort_fallback"};
 
 int32_t ksum_stage_count(void) { return ST_COUNT; }
 
