@@ -91,6 +91,56 @@ def kernel_work(stage, wl, P):
     return "hbm", gb / 1e9, "GB/s", PEAK_HBM_GBS
 
 
+# stage -> (kernel name prefix in the rocprofv3 summaries, source file of the kernel)
+STAGE_KERNEL = {
+    "project": ("proj_gemm_kernel", "k_project.hip"),
+    "sort_group": ("sort_fast_kernel", "k_sort.hip"),
+    "sort_scatter": ("sort_scatter_kernel", "k_sort.hip"),
+    "sort_hist": ("sort_hist_kernel", "k_sort.hip"),
+    "nfft_spread": ("nfft_spread_kernel", "k_fourier.hip"),
+    "nfft_interp": ("nfft_interp_accum_kernel", "k_fourier.hip"),
+    "ndft_adjoint": ("ndft_adjoint_kernel", "k_fourier.hip"),
+    "ndft_forward": ("ndft_forward_kernel", "k_fourier.hip"),
+    "accumulate": ("accumulate_kernel", "k_reduce.hip"),
+}
+WORKLOAD_TAG = {"negdist": "negdist_N1e5_d784_P256", "laplace": "laplace_N2e5_d3072_P512",
+                "gauss_nfft": "gauss_nfft_N1e6_d50_P256", "gauss_ndft": "gauss_ndft_N1e3_d10_P64"}
+
+
+def source_digest(fname):
+    import hashlib
+    h = hashlib.sha256()
+    for g in (fname, "device_common.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2401_08260_amd", "csrc", g), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, stage):
+    """HBM bytes per launch of a stage's kernel from the committed FETCH_SIZE / WRITE_SIZE
+    summary (already scaled by the copy-kernel calibration), or None when there is no
+    summary or the kernel's source differs from the one the counters were taken with."""
+    if stage not in STAGE_KERNEL or workload not in WORKLOAD_TAG:
+        return None
+    kname, src = STAGE_KERNEL[stage]
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{WORKLOAD_TAG[workload]}.md")
+    if not os.path.exists(path):
+        return None
+    rd = wr = None
+    digest = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("| `" + kname):
+                cols = [c.strip() for c in line.strip().strip("|").split("|")]
+                rd, wr = float(cols[3]), float(cols[4])
+            elif line.startswith("- source-digest " + src + " "):
+                digest = line.split()[-1]
+    if rd is None or digest != source_digest(src):
+        return None
+    return {"read_GB": rd, "write_GB": wr, "total_GB": rd + wr,
+            "source": os.path.relpath(path, ROOT)}
+
+
 def cpu_baseline(wl, x, y, w, sigma, xi, s_gpu, t_gpu, budget_s, exact_targets):
     """Oracle timing on a bounded sample + errors of the GPU result (oracle leg)."""
     from oracle import direct, sliced
@@ -207,8 +257,11 @@ def main():
     dom = max((k for k in stage_share if kernel_work(k, wl, wl.P)), key=lambda k: stage_share[k])
     bound, amount, unit, peak = kernel_work(dom, wl, wl.P)
     achieved = amount / (stage_ms[dom] * 1e-3)
+    tr = measured_traffic(wl.name, dom)
     roofline = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": None, "avg_launch_ms": stage_ms[dom],
+                "frac": achieved / peak, "traffic": tr["total_GB"] if tr else None,
+                "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "traffic_detail": tr, "avg_launch_ms": stage_ms[dom],
                 "share_of_step": stage_share[dom] / ms}
 
     result = {

@@ -22,6 +22,7 @@ constexpr int BM = kGemmBM;   // 128 slices
 constexpr int BN = 128;       // points
 constexpr int BK = kGemmBK;   // 16
 constexpr int LDA = BK + 4;   // padded LDS row (80 B): conflict-free 16-byte reads per 16 lanes
+constexpr int LDC = BN + 4;   // padded row of the staged output tile
 
 // Loads the BN x BK tile of union rows [l0, l0+BN) and columns [k0, k0+BK) into
 // registers, 2 groups of 4 consecutive columns per thread, VW elements per load
@@ -32,39 +33,34 @@ struct PointLoader {
   int64_t N, M, L;
   int d;
 
-  __device__ __forceinline__ void load(int64_t l0, int k0, float4 (&r)[2]) const {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int e = t + i * 256;
-      const int row = e >> 2, k4 = (e & 3) * 4;
-      const int64_t l = l0 + row;
-      const int k = k0 + k4;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (l < L) {
-        const InT *src = (l < M) ? (y + l * (int64_t)d) : (x + (l - M) * (int64_t)d);
-        if constexpr (VW == 4) {
-          if (k < d) v = *reinterpret_cast<const float4 *>(src + k);
-        } else if constexpr (VW == 2) {
-          if (k < d) {
-            const float2 q = *reinterpret_cast<const float2 *>(src + k);
-            v.x = q.x;
-            v.y = q.y;
-          }
-          if (k + 2 < d) {
-            const float2 q = *reinterpret_cast<const float2 *>(src + k + 2);
-            v.z = q.x;
-            v.w = q.y;
-          }
-        } else {
-          if (k + 0 < d) v.x = (float)src[k + 0];
-          if (k + 1 < d) v.y = (float)src[k + 1];
-          if (k + 2 < d) v.z = (float)src[k + 2];
-          if (k + 3 < d) v.w = (float)src[k + 3];
+  __device__ __forceinline__ float4 load1(int64_t l0, int k0, int e) const {
+    const int row = e >> 2, k4 = (e & 3) * 4;
+    const int64_t l = l0 + row;
+    const int k = k0 + k4;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (l < L) {
+      const InT *src = (l < M) ? (y + l * (int64_t)d) : (x + (l - M) * (int64_t)d);
+      if constexpr (VW == 4) {
+        if (k < d) v = *reinterpret_cast<const float4 *>(src + k);
+      } else if constexpr (VW == 2) {
+        if (k < d) {
+          const float2 q = *reinterpret_cast<const float2 *>(src + k);
+          v.x = q.x;
+          v.y = q.y;
         }
+        if (k + 2 < d) {
+          const float2 q = *reinterpret_cast<const float2 *>(src + k + 2);
+          v.z = q.x;
+          v.w = q.y;
+        }
+      } else {
+        if (k + 0 < d) v.x = (float)src[k + 0];
+        if (k + 1 < d) v.y = (float)src[k + 1];
+        if (k + 2 < d) v.z = (float)src[k + 2];
+        if (k + 3 < d) v.w = (float)src[k + 3];
       }
-      r[i] = v;
     }
+    return v;
   }
 };
 
@@ -76,6 +72,7 @@ struct GemmCtl {
   uint32_t *counter;      // tile queue head (zeroed before the launch)
   uint32_t *part;         // [gridDim.x][nsl][2] per-block min / max keys
   int n_col_tiles, n_row_tiles;
+  int z_vec4;             // Z rows are 16-byte aligned (ldz % 4 == 0): 16-byte stores
 };
 
 // Persistent blocks take (point tile, slice tile) work items from a device
@@ -85,8 +82,11 @@ struct GemmCtl {
 // kernel reduces the blocks' partials (no global atomics on 2P addresses).
 template <typename InT, int VW>
 __global__ __launch_bounds__(256) void proj_gemm_kernel(GemmCtl g, PointLoader<InT, VW> ld) {
-  __shared__ float As[2][BM * LDA];
-  __shared__ float Bs[2][BN * LDA];
+  // K-loop tiles As[2][BM][LDA], Bs[2][BN][LDA]; after the K loop the same memory
+  // stages half of the output tile (64 rows of LDC floats) for the epilogue
+  __shared__ __align__(16) float smem[2 * (BM + BN) * LDA];
+  auto As = [&](int b) { return smem + b * (BM * LDA); };
+  auto Bs = [&](int b) { return smem + 2 * BM * LDA + b * (BN * LDA); };
   __shared__ uint32_t smin[kMaxBatch], smax[kMaxBatch];
   __shared__ int s_tile;
 
@@ -119,39 +119,35 @@ __global__ __launch_bounds__(256) void proj_gemm_kernel(GemmCtl g, PointLoader<I
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    auto load_a = [&](int k0, float4 (&r)[2]) {
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int e = t + i * 256;
-        const int row = e >> 2, k4 = (e & 3) * 4;
-        r[i] = *reinterpret_cast<const float4 *>(A + (int64_t)row * g.d_pad + k0 + k4);
-      }
+    // element e of the 512 float4 of a 128 x 16 tile: row e / 4, columns 4 (e % 4) .. + 3
+    auto load_a = [&](int k0, int e) {
+      const int row = e >> 2, k4 = (e & 3) * 4;
+      return *reinterpret_cast<const float4 *>(A + (int64_t)row * g.d_pad + k0 + k4);
     };
-    auto store_tile = [&](float *S, const float4 (&r)[2]) {
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int e = t + i * 256;
-        const int row = e >> 2, k4 = (e & 3) * 4;
-        *reinterpret_cast<float4 *>(S + row * LDA + k4) = r[i];
-      }
+    auto store4 = [&](float *S, int e, float4 v) {
+      const int row = e >> 2, k4 = (e & 3) * 4;
+      *reinterpret_cast<float4 *>(S + row * LDA + k4) = v;
     };
 
-    float4 ra[2], rb[2];
-    load_a(0, ra);
-    ld.load(l0, 0, rb);
-    store_tile(As[0], ra);
-    store_tile(Bs[0], rb);
+    float4 ra0 = load_a(0, t), ra1 = load_a(0, t + 256);
+    float4 rb0 = ld.load1(l0, 0, t), rb1 = ld.load1(l0, 0, t + 256);
+    store4(As(0), t, ra0);
+    store4(As(0), t + 256, ra1);
+    store4(Bs(0), t, rb0);
+    store4(Bs(0), t + 256, rb1);
     __syncthreads();
 
     for (int kb = 0; kb < nk; ++kb) {
       const int cur = kb & 1;
       const bool more = kb + 1 < nk;
       if (more) {
-        load_a((kb + 1) * BK, ra);
-        ld.load(l0, (kb + 1) * BK, rb);
+        ra0 = load_a((kb + 1) * BK, t);
+        ra1 = load_a((kb + 1) * BK, t + 256);
+        rb0 = ld.load1(l0, (kb + 1) * BK, t);
+        rb1 = ld.load1(l0, (kb + 1) * BK, t + 256);
       }
-      const float *pa0 = As[cur] + (wm * 64 + lr) * LDA + lh * 8;
-      const float *pb0 = Bs[cur] + (wn * 64 + lr) * LDA + lh * 8;
+      const float *pa0 = As(cur) + (wm * 64 + lr) * LDA + lh * 8;
+      const float *pb0 = Bs(cur) + (wn * 64 + lr) * LDA + lh * 8;
       const float4 alo0 = *reinterpret_cast<const float4 *>(pa0);
       const float4 alo1 = *reinterpret_cast<const float4 *>(pa0 + 32 * LDA);
       const float4 blo0 = *reinterpret_cast<const float4 *>(pb0);
@@ -179,39 +175,72 @@ __global__ __launch_bounds__(256) void proj_gemm_kernel(GemmCtl g, PointLoader<I
           for (int j = 0; j < 2; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ah[i][s], bh[j][s], acc[i][j], 0, 0, 0);
       if (more) {
-        store_tile(As[cur ^ 1], ra);
-        store_tile(Bs[cur ^ 1], rb);
+        store4(As(cur ^ 1), t, ra0);
+        store4(As(cur ^ 1), t + 256, ra1);
+        store4(Bs(cur ^ 1), t, rb0);
+        store4(Bs(cur ^ 1), t + 256, rb1);
       }
       __syncthreads();
     }
 
-    // Epilogue: store Z (slice-major) and fold the tile into the block's min / max.
+    // Epilogue, in two halves of 64 slices: the waves holding the half write their
+    // accumulators to LDS, then every thread takes 16 values of one row (4 float4
+    // at a stride of 32 columns, so 8 neighbouring threads cover 128 contiguous
+    // bytes per store), writes them to Z and folds them into the row's min / max.
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int h = 0; h < 2; ++h) {
+      if (wm == h) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = r0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);   // local slice
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+              smem[(i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3)) * LDC + wn * 64 + j * 32 + lr] = acc[i][j][r];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int lrow = q * 32 + (t >> 3);            // row within the half
+        const int row = r0 + h * 64 + lrow;            // slice within the batch
+        const int c0 = (t & 7) * 4;
         float vmin = __builtin_huge_valf(), vmax = -__builtin_huge_valf();
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int64_t l = l0 + wn * 64 + j * 32 + lr;
-          const float v = acc[i][j][r];
-          if (row < g.nsl && l < ld.L) {
-            g.Z[(int64_t)row * g.ldz + l] = v;
-            vmin = fminf(vmin, v);
-            vmax = fmaxf(vmax, v);
+        for (int k = 0; k < 4; ++k) {
+          const int c = c0 + 32 * k;
+          const float4 v = *reinterpret_cast<const float4 *>(smem + lrow * LDC + c);
+          const int64_t l = l0 + c;
+          if (row < g.nsl) {
+            float *dst = g.Z + (int64_t)row * g.ldz + l;
+            if (g.z_vec4 && l + 3 < ld.L) {
+              *reinterpret_cast<float4 *>(dst) = v;
+            } else {
+              if (l + 0 < ld.L) dst[0] = v.x;
+              if (l + 1 < ld.L) dst[1] = v.y;
+              if (l + 2 < ld.L) dst[2] = v.z;
+              if (l + 3 < ld.L) dst[3] = v.w;
+            }
+          }
+          if (l + 3 < ld.L) {
+            vmin = fminf(vmin, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
+            vmax = fmaxf(vmax, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
+          } else {
+            if (l + 0 < ld.L) { vmin = fminf(vmin, v.x); vmax = fmaxf(vmax, v.x); }
+            if (l + 1 < ld.L) { vmin = fminf(vmin, v.y); vmax = fmaxf(vmax, v.y); }
+            if (l + 2 < ld.L) { vmin = fminf(vmin, v.z); vmax = fmaxf(vmax, v.z); }
           }
         }
 #pragma unroll
-        for (int off = 1; off < 32; off <<= 1) {
+        for (int off = 1; off < 8; off <<= 1) {
           vmin = fminf(vmin, __shfl_xor(vmin, off, 64));
           vmax = fmaxf(vmax, __shfl_xor(vmax, off, 64));
         }
-        if (lr == 0 && row < g.nsl && vmin <= vmax) {
+        if ((t & 7) == 0 && row < g.nsl && vmin <= vmax) {
           atomicMin(&smin[row], float_key(vmin));
           atomicMax(&smax[row], float_key(vmax));
         }
       }
+      __syncthreads();
     }
   }
   __syncthreads();
@@ -245,6 +274,7 @@ hipError_t launch_projection(const ExecArgs &a) {
   g.part = wsp<uint32_t>(a, lay.off_bounds_part);
   g.n_col_tiles = (int)((lay.L + BN - 1) / BN);
   g.n_row_tiles = (a.nsl + BM - 1) / BM;
+  g.z_vec4 = (lay.L % 4 == 0) ? 1 : 0;
   const unsigned grid = (unsigned)projection_blocks(lay.L, a.nsl);
   mark(a, ST_MISC);
   gemm_init_kernel<<<1, 64, 0, a.stream>>>(g.counter);

@@ -116,7 +116,7 @@ Layout make_layout(const ksum_plan &pl, int64_t N, int64_t M) {
   y.off_params = take(B * sizeof(SliceParams));
   y.off_bounds = take(B * 2 * sizeof(uint32_t));
   y.off_counter = take(64);
-  y.off_bounds_part = take((size_t)projection_blocks(y.L, (int)B) * B * 2 * sizeof(uint32_t));
+  y.off_bounds_part = take((size_t)256 * kGemmBlocksPerCU * B * 2 * sizeof(uint32_t));
   y.off_z = take((size_t)B * y.L * sizeof(float));
   // per-slice sums that pass through HBM: NDFT output and the negative-distance sort
   // output (t1), the Laplacian's sorted part (t2); the NFFT interpolation adds its
