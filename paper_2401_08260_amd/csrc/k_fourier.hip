@@ -178,13 +178,13 @@ __device__ __forceinline__ void window_taps(const WindowPoly &wp, float x, float
   }
 }
 
-template <int MW, int DEG>
-__global__ __launch_bounds__(256) void nfft_spread_kernel(FourierArgs a) {
-  extern __shared__ float acc[];   // [W][lanes]
+template <int MW, int DEG, int LANES>
+__global__ __launch_bounds__(LANES) void nfft_spread_kernel(FourierArgs a) {
+  extern __shared__ float acc[];   // [W][LANES]
   const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * a.chunks);
   if (work < 0) return;
   const int p = (int)(work / a.chunks), c = (int)(work % a.chunks);
-  const int lanes = a.lanes;
+  const int lanes = LANES;
   const int t = threadIdx.x;
   for (int i = t; i < a.W * lanes; i += lanes) acc[i] = 0.f;
   __syncthreads();
@@ -202,9 +202,13 @@ __global__ __launch_bounds__(256) void nfft_spread_kernel(FourierArgs a) {
     float tap[2 * MW];
     window_taps<MW, DEG>(a.poly, fr - 0.5f, tap);
     const float wv = a.w[i];
+    // the 2 MW cells of this lane's window copy are distinct: read them all, then write
     float *base = acc + (i0 - MW + 1 - a.lo) * lanes + t;
+    float v[2 * MW];
 #pragma unroll
-    for (int j = 0; j < 2 * MW; ++j) base[j * lanes] += wv * tap[j];
+    for (int j = 0; j < 2 * MW; ++j) v[j] = base[j * lanes];
+#pragma unroll
+    for (int j = 0; j < 2 * MW; ++j) base[j * lanes] = fmaf(wv, tap[j], v[j]);
   }
   __syncthreads();
   // reduce the lanes of every cell in a fixed order: one wave per cell
@@ -360,14 +364,24 @@ static void launch_nfft_m(const FourierArgs &f, const ExecArgs &a) {
   const unsigned gs = (unsigned)xcd_grid((int64_t)a.nsl * f.chunks);
   const size_t spread_lds = (size_t)f.W * f.lanes * sizeof(float);
   const size_t grid_lds = 2 * (size_t)f.n * sizeof(float2);
-  if (spread_lds > 65536)
-    (void)hipFuncSetAttribute((const void *)nfft_spread_kernel<MW, DEG>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)spread_lds);
+  if (spread_lds > 65536) {
+    (void)hipFuncSetAttribute((const void *)nfft_spread_kernel<MW, DEG, 256>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)spread_lds);
+    (void)hipFuncSetAttribute((const void *)nfft_spread_kernel<MW, DEG, 128>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)spread_lds);
+    (void)hipFuncSetAttribute((const void *)nfft_spread_kernel<MW, DEG, 64>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)spread_lds);
+  }
   if (grid_lds > 65536)
     (void)hipFuncSetAttribute((const void *)nfft_grid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)grid_lds);
   mark(a, ST_NFFT_SPREAD);
-  nfft_spread_kernel<MW, DEG><<<gs, f.lanes, spread_lds, a.stream>>>(f);
+  if (f.lanes == 256)
+    nfft_spread_kernel<MW, DEG, 256><<<gs, 256, spread_lds, a.stream>>>(f);
+  else if (f.lanes == 128)
+    nfft_spread_kernel<MW, DEG, 128><<<gs, 128, spread_lds, a.stream>>>(f);
+  else
+    nfft_spread_kernel<MW, DEG, 64><<<gs, 64, spread_lds, a.stream>>>(f);
   mark(a, ST_NFFT_GRID);
   nfft_grid_kernel<<<a.nsl, 256, grid_lds, a.stream>>>(f);
 }
@@ -411,13 +425,13 @@ static FourierArgs nfft_args(const ExecArgs &a) {
 hipError_t launch_nfft(const ExecArgs &a) {
   const FourierArgs f = nfft_args(a);
   switch (a.plan->params.window_m) {
-    case 2: launch_nfft_m<2, 10>(f, a); break;
-    case 3: launch_nfft_m<3, 10>(f, a); break;
-    case 4: launch_nfft_m<4, 10>(f, a); break;
-    case 5: launch_nfft_m<5, 10>(f, a); break;
-    case 6: launch_nfft_m<6, 10>(f, a); break;
-    case 7: launch_nfft_m<7, 12>(f, a); break;
-    case 8: launch_nfft_m<8, 12>(f, a); break;
+    case 2: launch_nfft_m<2, 9>(f, a); break;
+    case 3: launch_nfft_m<3, 9>(f, a); break;
+    case 4: launch_nfft_m<4, 9>(f, a); break;
+    case 5: launch_nfft_m<5, 9>(f, a); break;
+    case 6: launch_nfft_m<6, 8>(f, a); break;
+    case 7: launch_nfft_m<7, 8>(f, a); break;
+    case 8: launch_nfft_m<8, 8>(f, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -446,18 +460,20 @@ hipError_t launch_nfft_interp(const ExecArgs &a, float *s, bool first, bool last
   c.invP = 1.0 / (double)pl.P;
   c.tpt = (int)std::max<int64_t>(1, std::min<int64_t>(4, lay.M / (256 * 1024)));
   switch (pl.params.window_m) {
-    case 2: launch_interp_m<2, 10>(f, c, a); break;
-    case 3: launch_interp_m<3, 10>(f, c, a); break;
-    case 4: launch_interp_m<4, 10>(f, c, a); break;
-    case 5: launch_interp_m<5, 10>(f, c, a); break;
-    case 6: launch_interp_m<6, 10>(f, c, a); break;
-    case 7: launch_interp_m<7, 12>(f, c, a); break;
-    case 8: launch_interp_m<8, 12>(f, c, a); break;
+    case 2: launch_interp_m<2, 9>(f, c, a); break;
+    case 3: launch_interp_m<3, 9>(f, c, a); break;
+    case 4: launch_interp_m<4, 9>(f, c, a); break;
+    case 5: launch_interp_m<5, 9>(f, c, a); break;
+    case 6: launch_interp_m<6, 8>(f, c, a); break;
+    case 7: launch_interp_m<7, 8>(f, c, a); break;
+    case 8: launch_interp_m<8, 8>(f, c, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-int window_degree_for(int m) { return m <= 6 ? 10 : 12; }
+// Degree of the per-tap window polynomials: the smallest that fits the Kaiser-Bessel
+// taps to about 1e-8 of phi(0) for oversampling 2..8 (narrow windows are steeper per cell).
+int window_degree_for(int m) { return m <= 5 ? 9 : 8; }
 
 }  // namespace ksum
