@@ -49,8 +49,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def plan_kwargs(wl, sigma):
-    kw = dict(seed=wl.dir_seed)
+def plan_kwargs(wl, sigma, precision="fp32"):
+    kw = dict(seed=wl.dir_seed, precision=precision)
     if wl.kernel != "negdist":
         kw.update(sigma=sigma, n_coeff=wl.n_coeff, T=wl.T, method=wl.method)
         if wl.method == "nfft":
@@ -141,7 +141,7 @@ def measured_traffic(workload, stage):
             "source": os.path.relpath(path, ROOT)}
 
 
-def cpu_baseline(wl, x, y, w, sigma, xi, s_gpu, t_gpu, budget_s, exact_targets):
+def cpu_baseline(wl, x, y, w, sigma, xi, s_gpu, t_gpu, budget_s, exact_targets, s_mixed=None):
     """Oracle timing on a bounded sample + errors of the GPU result (oracle leg)."""
     from oracle import direct, sliced
 
@@ -163,7 +163,12 @@ def cpu_baseline(wl, x, y, w, sigma, xi, s_gpu, t_gpu, budget_s, exact_targets):
            "sample": f"first {Q} of {wl.P} slices at full N={wl.N}, M={wl.M}, d={wl.d} "
                      f"({dt:.1f} s; FP64 projection + per-slice 1-D fast sum)"}
     # parity of the GPU per-slice sums on the sampled slices
-    par = sliced.rel_l2(t_gpu[:Q].astype(np.float64), ts) if t_gpu is not None else None
+    if t_gpu is not None:
+        par = sliced.rel_l2(t_gpu[:Q].astype(np.float64), ts)
+    elif Q == wl.P:   # every slice was sampled: compare the averages
+        par = sliced.rel_l2(s_gpu.astype(np.float64), ts.mean(axis=0))
+    else:
+        par = None
     # error of the GPU result against the exact sum on a subsample of targets (also timed)
     k = min(exact_targets, wl.M)
     t0 = time.perf_counter()
@@ -175,6 +180,10 @@ def cpu_baseline(wl, x, y, w, sigma, xi, s_gpu, t_gpu, budget_s, exact_targets):
             "exact_per_summand": sliced.per_summand_error(s_sub, ex, w),
             "exact_targets": k,
             "direct_pairs_per_s": float(k) * wl.N / dte}
+    if s_mixed is not None:
+        sm = s_mixed[:k].astype(np.float64)
+        errs["mixed_exact_rel_l2"] = sliced.rel_l2(sm, ex)
+        errs["mixed_exact_per_summand"] = sliced.per_summand_error(sm, ex, w)
     return out, errs
 
 
@@ -187,6 +196,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in the CPU leg")
     ap.add_argument("--exact-targets", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the split-BF16 (mixed) leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device (reference for the HBM traffic counters)")
     args = ap.parse_args()
@@ -264,6 +274,35 @@ def main():
                 "traffic_detail": tr, "avg_launch_ms": stage_ms[dom],
                 "share_of_step": stage_share[dom] / ms}
 
+    # timed region 3: the same step with the split-BF16 projection ("mixed")
+    mixed = None
+    s_mixed = None
+    if not args.no_mixed:
+        plan_m = ks.Plan(wl.d, wl.P, wl.kernel, **plan_kwargs(wl, sigma, "split_bf16"))
+        sm = torch.empty(wl.M, dtype=torch.float32, device=dev)
+        for _ in range(args.warmup):
+            plan_m(xt, yt, wt, out=sm)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            plan_m(xt, yt, wt, out=sm)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_m = float(e0.elapsed_time(e1)) / args.steps
+        ks.ksum_set_timing(plan_m.handle, True)
+        plan_m(xt, yt, wt, out=sm)
+        torch.cuda.synchronize()
+        st_m = ks.ksum_stage_times(plan_m.handle)
+        ks.ksum_set_timing(plan_m.handle, False)
+        s_mixed = sm.cpu().numpy().astype(np.float64)
+        s_fp32 = s.cpu().numpy().astype(np.float64)
+        mixed = {"precision": "split_bf16", "ms_per_step": ms_m, "value": wl.M * wl.P / (ms_m * 1e-3),
+                 "speedup_vs_fp32": ms / ms_m, "project_ms": st_m["project"][0] if "project" in st_m else None,
+                 "rel_l2_vs_fp32_result": float(np.linalg.norm(s_mixed - s_fp32) / np.linalg.norm(s_fp32))}
+        log(f"[bench] mixed (split-BF16 projection): {ms_m:.3f} ms/step, {mixed['value']:.4e} {UNIT}, "
+            f"x{mixed['speedup_vs_fp32']:.2f} vs FP32")
+
     result = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "p50_ms": float(np.percentile(per, 50)),
@@ -274,16 +313,16 @@ def main():
                    "input": wl.dtype, "sigma": sigma},
         "stage_ms_per_step": stage_share,
         "roofline": roofline,
+        "mixed": mixed,
     }
 
     if not args.no_cpu_baseline:
         probe_t = torch.empty((wl.P, wl.M), dtype=torch.float32, device=dev)
-        if wl.dtype == "f32":
-            plan(xt, yt, wt, out=s, probe={"t": probe_t})
+        plan(xt, yt, wt, out=s, probe={"t": probe_t})
         torch.cuda.synchronize()
         base, errs = cpu_baseline(wl, x, y, w, sigma, plan.directions(), s.cpu().numpy(),
-                                  probe_t.cpu().numpy() if wl.dtype == "f32" else None, args.cpu_budget,
-                                  args.exact_targets)
+                                  probe_t.cpu().numpy(), args.cpu_budget,
+                                  args.exact_targets, s_mixed)
         result["cpu_baseline"] = base
         result["errors"] = errs
         log(f"[bench] cpu baseline {base['value']:.3e} {UNIT} ({base['sample']}); errors {errs}")

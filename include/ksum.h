@@ -62,7 +62,13 @@ typedef enum {
   KSUM_1D_SORT = 3
 } ksum_method;
 
-/* Arithmetic of the projection GEMM.  FP32 uses FP32 matrix cores. */
+/* Arithmetic of the projection GEMM (the first step of Algorithm "Sliced Fast
+ * Fourier Summation").  FP32 uses the FP32 matrix cores.  SPLIT_BF16 splits every
+ * FP32 operand a into a_hi = bf16(a) and a_lo = bf16(a - a_hi) (round to nearest
+ * even) and takes a product as a_hi b_hi + a_hi b_lo + a_lo b_hi on the BF16 matrix
+ * cores with FP32 accumulation: each product is within about 2^-16 of the FP32
+ * product.  Everything after the projection is the same FP32 / FP64 arithmetic in
+ * both modes. */
 typedef enum {
   KSUM_FP32 = 0,
   KSUM_SPLIT_BF16 = 1
@@ -193,6 +199,12 @@ ksum_status ksum_execute_f64in(ksum_plan *plan, const double *x, int64_t N, cons
 ksum_status ksum_execute_probe(ksum_plan *plan, const float *x, int64_t N, const float *y, int64_t M,
                                const float *w, float *s, void *ws, size_t ws_bytes, void *stream,
                                const ksum_probe *probe);
+
+/* As ksum_execute_probe with FP64 inputs x, y, w (converted to FP32 as they are read;
+ * the probed z are the FP32 projections of the converted inputs). */
+ksum_status ksum_execute_probe_f64in(ksum_plan *plan, const double *x, int64_t N, const double *y, int64_t M,
+                                     const double *w, float *s, void *ws, size_t ws_bytes, void *stream,
+                                     const ksum_probe *probe);
 
 /* Per-kernel timing (diagnostic).  While enabled, ksum_execute records HIP events
  * on its stream around every kernel it launches (a few microseconds of overhead

@@ -27,6 +27,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 KSUM_GAUSSIAN, KSUM_LAPLACIAN, KSUM_NEGDIST = 1, 2, 3
 KSUM_1D_AUTO, KSUM_1D_NDFT, KSUM_1D_NFFT, KSUM_1D_SORT = 0, 1, 2, 3
 KSUM_FP32, KSUM_SPLIT_BF16 = 0, 1
+PRECISIONS = {"fp32": KSUM_FP32, "split_bf16": KSUM_SPLIT_BF16}
 KSUM_OK, KSUM_EINVAL, KSUM_EUNSUPPORTED, KSUM_ENOMEM, KSUM_EWORKSPACE, KSUM_ENONFINITE, KSUM_EDEVICE = range(7)
 
 KERNELS = {"gaussian": KSUM_GAUSSIAN, "laplacian": KSUM_LAPLACIAN, "negdist": KSUM_NEGDIST}
@@ -66,6 +67,8 @@ _sigs = {
                                           _P]),
     "ksum_execute_probe": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P, ctypes.c_size_t,
                                           _P, ctypes.POINTER(ksum_probe)]),
+    "ksum_execute_probe_f64in": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P,
+                                                ctypes.c_size_t, _P, ctypes.POINTER(ksum_probe)]),
     "ksum_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ksum_stage_times": (ctypes.c_int, [_P, _P, _P]),
     "ksum_stage_count": (ctypes.c_int32, []),
@@ -118,6 +121,8 @@ def make_params(kernel: int, directions: Optional[np.ndarray] = None, **override
     for k, v in overrides.items():
         if k == "method" and isinstance(v, str):
             v = METHODS[v]
+        if k == "precision" and isinstance(v, str):
+            v = PRECISIONS[v]
         if not hasattr(p, k):
             raise TypeError(f"unknown parameter {k}")
         setattr(p, k, v)
@@ -182,6 +187,13 @@ def ksum_execute_probe(plan: int, x: int, N: int, y: int, M: int, w: int, s: int
                        stream: int, probe: Optional[ksum_probe]) -> None:
     _check(_lib.ksum_execute_probe(plan, x, N, y, M, w, s, ws, ws_bytes, stream,
                                    ctypes.byref(probe) if probe is not None else None), "ksum_execute_probe")
+
+
+def ksum_execute_probe_f64in(plan: int, x: int, N: int, y: int, M: int, w: int, s: int, ws: int,
+                             ws_bytes: int, stream: int, probe: Optional[ksum_probe]) -> None:
+    _check(_lib.ksum_execute_probe_f64in(plan, x, N, y, M, w, s, ws, ws_bytes, stream,
+                                         ctypes.byref(probe) if probe is not None else None),
+           "ksum_execute_probe_f64in")
 
 
 def ksum_set_timing(plan: int, enable: bool) -> None:
@@ -259,12 +271,11 @@ class Plan:
         ws, need = self.workspace(N, M, x.device)
         st = (stream if stream is not None else torch.cuda.current_stream(x.device)).cuda_stream
         if probe is not None:
-            if f64:
-                raise TypeError("probes take FP32 inputs")
             pr = ksum_probe(*(probe[k].data_ptr() if probe.get(k) is not None else None
                               for k in ("z", "bounds", "t", "perm")))
-            ksum_execute_probe(self.handle, x.data_ptr(), N, y.data_ptr(), M, w.data_ptr(), s.data_ptr(),
-                               ws.data_ptr(), ws.numel(), st, pr)
+            fn = ksum_execute_probe_f64in if f64 else ksum_execute_probe
+            fn(self.handle, x.data_ptr(), N, y.data_ptr(), M, w.data_ptr(), s.data_ptr(),
+               ws.data_ptr(), ws.numel(), st, pr)
         elif f64:
             ksum_execute_f64in(self.handle, x.data_ptr(), N, y.data_ptr(), M, w.data_ptr(), s.data_ptr(),
                                ws.data_ptr(), ws.numel(), st)

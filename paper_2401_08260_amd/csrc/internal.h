@@ -86,6 +86,8 @@ struct ksum_plan {
   ksum::WindowPoly poly{};
   // device tables
   float *d_dirs = nullptr;       // [P_pad][d_pad] FP32, zero padded
+  uint16_t *d_dirs_hi = nullptr; // [P_pad][d_pad] bf16 hi half of the FP32 directions (split-BF16)
+  uint16_t *d_dirs_lo = nullptr; // [P_pad][d_pad] bf16 lo half (split-BF16)
   float *d_deconv = nullptr;     // [K+1] 1 / (n phihat(k))^2 (NFFT)
   float2 *d_twiddle = nullptr;   // [n_grid] exp(-2 pi i j / n)
   double *d_costab = nullptr;    // [lap_L] cos(2 pi j / lap_L)
@@ -170,7 +172,10 @@ inline void mark(const ExecArgs &a, int stage) {
 
 hipError_t launch_weight_prep(const ExecArgs &a, const double *w64);
 hipError_t launch_projection(const ExecArgs &a);
-int projection_blocks(int64_t L, int nsl);
+struct GemmCtl;
+hipError_t launch_projection_bf16x3(const ExecArgs &a, GemmCtl g);
+int projection_bf16x3_blocks(int64_t L, int nsl);
+int projection_blocks(const ksum_plan &plan, int64_t L, int nsl);
 hipError_t launch_slice_setup(const ExecArgs &a);
 hipError_t launch_ndft(const ExecArgs &a);
 hipError_t launch_nfft(const ExecArgs &a);

@@ -11,8 +11,7 @@
 // consecutive floats of its row with two 16-byte LDS loads.
 #include <algorithm>
 
-#include "device_common.h"
-#include "internal.h"
+#include "project_common.h"
 
 namespace ksum {
 
@@ -23,57 +22,6 @@ constexpr int BN = 128;       // points
 constexpr int BK = kGemmBK;   // 16
 constexpr int LDA = BK + 4;   // padded LDS row (80 B): conflict-free 16-byte reads per 16 lanes
 constexpr int LDC = BN + 4;   // padded row of the staged output tile
-
-// Loads the BN x BK tile of union rows [l0, l0+BN) and columns [k0, k0+BK) into
-// registers, 2 groups of 4 consecutive columns per thread, VW elements per load
-// (VW = 4: 16-byte loads, d % 4 == 0; VW = 2: 8-byte loads, d even; VW = 1: any d).
-template <typename InT, int VW>
-struct PointLoader {
-  const InT *x, *y;
-  int64_t N, M, L;
-  int d;
-
-  __device__ __forceinline__ float4 load1(int64_t l0, int k0, int e) const {
-    const int row = e >> 2, k4 = (e & 3) * 4;
-    const int64_t l = l0 + row;
-    const int k = k0 + k4;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (l < L) {
-      const InT *src = (l < M) ? (y + l * (int64_t)d) : (x + (l - M) * (int64_t)d);
-      if constexpr (VW == 4) {
-        if (k < d) v = *reinterpret_cast<const float4 *>(src + k);
-      } else if constexpr (VW == 2) {
-        if (k < d) {
-          const float2 q = *reinterpret_cast<const float2 *>(src + k);
-          v.x = q.x;
-          v.y = q.y;
-        }
-        if (k + 2 < d) {
-          const float2 q = *reinterpret_cast<const float2 *>(src + k + 2);
-          v.z = q.x;
-          v.w = q.y;
-        }
-      } else {
-        if (k + 0 < d) v.x = (float)src[k + 0];
-        if (k + 1 < d) v.y = (float)src[k + 1];
-        if (k + 2 < d) v.z = (float)src[k + 2];
-        if (k + 3 < d) v.w = (float)src[k + 3];
-      }
-    }
-    return v;
-  }
-};
-
-struct GemmCtl {
-  const float *dirs;
-  int d_pad, p0, nsl;
-  float *Z;
-  int64_t ldz;
-  uint32_t *counter;      // tile queue head (zeroed before the launch)
-  uint32_t *part;         // [gridDim.x][nsl][2] per-block min / max keys
-  int n_col_tiles, n_row_tiles;
-  int z_vec4;             // Z rows are 16-byte aligned (ldz % 4 == 0): 16-byte stores
-};
 
 // Persistent blocks take (point tile, slice tile) work items from a device
 // counter in order, so neighbouring items (the slice tiles of one point tile)
@@ -255,7 +203,8 @@ __global__ void gemm_init_kernel(uint32_t *counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
 
-int projection_blocks(int64_t L, int nsl) {
+int projection_blocks(const ksum_plan &plan, int64_t L, int nsl) {
+  if (plan.params.precision == KSUM_SPLIT_BF16) return projection_bf16x3_blocks(L, nsl);
   const int64_t tiles = ((L + BN - 1) / BN) * (int64_t)((nsl + BM - 1) / BM);
   return (int)std::min<int64_t>(tiles, 256 * kGemmBlocksPerCU);
 }
@@ -275,10 +224,13 @@ hipError_t launch_projection(const ExecArgs &a) {
   g.n_col_tiles = (int)((lay.L + BN - 1) / BN);
   g.n_row_tiles = (a.nsl + BM - 1) / BM;
   g.z_vec4 = (lay.L % 4 == 0) ? 1 : 0;
-  const unsigned grid = (unsigned)projection_blocks(lay.L, a.nsl);
+  g.dirs_hi = pl.d_dirs_hi;
+  g.dirs_lo = pl.d_dirs_lo;
   mark(a, ST_MISC);
   gemm_init_kernel<<<1, 64, 0, a.stream>>>(g.counter);
   mark(a, ST_PROJECT);
+  if (pl.params.precision == KSUM_SPLIT_BF16) return launch_projection_bf16x3(a, g);
+  const unsigned grid = (unsigned)projection_blocks(pl, lay.L, a.nsl);
   const int d = pl.d;
   const bool al16 = ((uintptr_t)a.x % 16 == 0) && ((uintptr_t)a.y % 16 == 0);
   const bool al8 = ((uintptr_t)a.x % 8 == 0) && ((uintptr_t)a.y % 8 == 0);

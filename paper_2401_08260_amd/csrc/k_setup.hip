@@ -182,7 +182,7 @@ hipError_t launch_slice_setup(const ExecArgs &a) {
   s.cd = pl.cd;
   s.bounds = wsp<uint32_t>(a, lay.off_bounds);
   s.part = wsp<uint32_t>(a, lay.off_bounds_part);
-  s.nparts = projection_blocks(lay.L, a.nsl);
+  s.nparts = projection_blocks(*a.plan, lay.L, a.nsl);
   s.misc = wsp<double>(a, lay.off_misc);
   s.deconv = pl.d_deconv;
   s.costab = pl.d_costab;

@@ -29,6 +29,21 @@ static ksum_status fail(ksum_status st, const std::string &msg) {
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// bfloat16 of a finite float, round to nearest even, and back
+static uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+static float bf16_to_float(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
 static int64_t next_pow2(int64_t v) {
   int64_t p = 1;
   while (p < v) p <<= 1;
@@ -68,7 +83,6 @@ static ksum_status validate(int32_t d, int32_t P, ksum_kernel kernel, const ksum
   if (p.method < KSUM_1D_AUTO || p.method > KSUM_1D_SORT) return fail(KSUM_EINVAL, "unknown method");
   if (p.precision != KSUM_FP32 && p.precision != KSUM_SPLIT_BF16)
     return fail(KSUM_EINVAL, "unknown precision");
-  if (p.precision == KSUM_SPLIT_BF16) return fail(KSUM_EUNSUPPORTED, "split-BF16 projection not built");
   if (p.slice_batch < 0) return fail(KSUM_EINVAL, "slice_batch must be >= 0");
   if (p.device < 0) return fail(KSUM_EINVAL, "device must be >= 0");
   if (kernel == KSUM_NEGDIST) {
@@ -185,6 +199,8 @@ static void free_plan(ksum_plan *pl) {
   if (!pl) return;
   free_timer(pl);
   if (pl->d_dirs) (void)hipFree(pl->d_dirs);
+  if (pl->d_dirs_hi) (void)hipFree(pl->d_dirs_hi);
+  if (pl->d_dirs_lo) (void)hipFree(pl->d_dirs_lo);
   if (pl->d_deconv) (void)hipFree(pl->d_deconv);
   if (pl->d_twiddle) (void)hipFree(pl->d_twiddle);
   if (pl->d_costab) (void)hipFree(pl->d_costab);
@@ -324,6 +340,20 @@ ksum_status ksum_plan_create(int32_t d, int32_t P, ksum_kernel kernel, const ksu
   if (hipMalloc(&pl->d_dirs, hd.size() * sizeof(float)) != hipSuccess) return dev_fail(KSUM_ENOMEM, "hipMalloc");
   if (hipMemcpy(pl->d_dirs, hd.data(), hd.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
     return dev_fail(KSUM_EDEVICE, "hipMemcpy");
+  if (pl->params.precision == KSUM_SPLIT_BF16) {
+    // hi = bf16(xi), lo = bf16(xi - hi) of the FP32 directions, round to nearest even
+    std::vector<uint16_t> hh(hd.size()), hl(hd.size());
+    for (size_t i = 0; i < hd.size(); ++i) {
+      hh[i] = bf16_rne(hd[i]);
+      hl[i] = bf16_rne(hd[i] - bf16_to_float(hh[i]));
+    }
+    const size_t nb = hd.size() * sizeof(uint16_t);
+    if (hipMalloc(&pl->d_dirs_hi, nb) != hipSuccess || hipMalloc(&pl->d_dirs_lo, nb) != hipSuccess)
+      return dev_fail(KSUM_ENOMEM, "hipMalloc");
+    if (hipMemcpy(pl->d_dirs_hi, hh.data(), nb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pl->d_dirs_lo, hl.data(), nb, hipMemcpyHostToDevice) != hipSuccess)
+      return dev_fail(KSUM_EDEVICE, "hipMemcpy");
+  }
   if (pl->method == KSUM_1D_NFFT) {
     const int n = pl->n_grid, m = pl->params.window_m, os = pl->params.oversample;
     // window normalised to phi(0) = 1 in the polynomials; deconvolution 1/(n phihat/phi0)^2
@@ -447,6 +477,12 @@ ksum_status ksum_execute_probe(ksum_plan *plan, const float *x, int64_t N, const
                                const float *w, float *s, void *ws, size_t ws_bytes, void *stream,
                                const ksum_probe *probe) {
   return execute_impl(plan, x, N, y, M, w, false, s, ws, ws_bytes, stream, probe);
+}
+
+ksum_status ksum_execute_probe_f64in(ksum_plan *plan, const double *x, int64_t N, const double *y, int64_t M,
+                                     const double *w, float *s, void *ws, size_t ws_bytes, void *stream,
+                                     const ksum_probe *probe) {
+  return execute_impl(plan, x, N, y, M, w, true, s, ws, ws_bytes, stream, probe);
 }
 
 static const char *kStageNames[ST_COUNT] = {

@@ -1,0 +1,111 @@
+"""GPU parity of the split-BF16 projection (precision="split_bf16") against the FP64 oracle.
+
+The split-BF16 GEMM takes every product as a_hi b_hi + a_hi b_lo + a_lo b_hi with
+a_hi = bf16(a), a_lo = bf16(a - a_hi).  With bf16's unit roundoff u = 2^-8 the
+dropped terms are a_lo b_lo and the residuals of the two splits, each at most
+about u^2 |a b|, so a product is within 3 u^2 |a b| (plus the FP32 rounding of
+the inputs and of the accumulation).  Everything after the projection is the
+FP32 / FP64 arithmetic of the FP32 path, so the end results differ from the FP32
+path only through the projection; their error against the oracle is printed and
+gated at MIXED_TOL.
+"""
+import numpy as np
+import pytest
+
+import workloads as wlm
+from oracle import sliced
+from test_gpu_parity import _check_perm, note, oracle_s, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+MIXED_TOL = 1e-4
+
+
+@pytest.mark.parametrize("N,M,d,P,f64", [(300, 200, 784, 16, False), (1000, 77, 50, 130, False),
+                                         (5, 3, 10, 1, False), (129, 1, 3, 2, False),
+                                         (513, 300, 33, 129, False), (700, 260, 12, 7, True)])
+def test_split_bf16_projection_bound(N, M, d, P, f64):
+    note(f"split-bf16 projection N={N} M={M} d={d} P={P} f64={f64}")
+    rng = np.random.default_rng(N + d)
+    dt = np.float64 if f64 else np.float32
+    x = rng.random((N, d)).astype(dt)
+    y = rng.standard_normal((M, d)).astype(dt)
+    w = np.full(N, 1.0 / N, dtype=dt)
+    r = run_gpu("negdist", x, y, w, P, seed=5, probe=True, precision="split_bf16")
+    xi = r["xi"]
+    u = np.concatenate([y, x]).astype(np.float64)
+    zref = (u @ xi.T).T
+    scale = (np.abs(u) @ np.abs(xi).T).T
+    bound = (4 * 2.0 ** -16 + 4 * d * 2.0 ** -24) * scale + 1e-30
+    err = np.abs(r["z"] - zref)
+    note(f"  max err / bound {np.max(err / bound):.3f}")
+    assert np.all(err <= bound)
+    z = r["z"].astype(np.float64)
+    assert np.array_equal(r["bounds"][:, 0], z.min(axis=1))
+    assert np.array_equal(r["bounds"][:, 1], z.max(axis=1))
+
+
+def test_split_bf16_negdist_parity_and_permutation():
+    rng = np.random.default_rng(77)
+    N, M, d, P = 6000, 5000, 784, 12
+    x = rng.random((N, d), dtype=np.float32)
+    y = rng.random((M, d), dtype=np.float32)
+    w = rng.random(N).astype(np.float32)
+    note(f"split-bf16 negdist N={N} M={M} d={d} P={P}")
+    r = run_gpu("negdist", x, y, w, P, seed=1, probe=True, precision="split_bf16")
+    _check_perm(r["z"], r["perm"])
+    ref = oracle_s("negdist", x, y, w, r["xi"])
+    err = sliced.rel_l2(r["s"], ref)
+    note(f"  rel err vs oracle {err:.3e}")
+    assert err <= MIXED_TOL
+
+
+def test_split_bf16_negdist_workload_full_size():
+    wl = wlm.WORKLOADS["negdist"]
+    x, y, w = wlm.generate(wl)
+    note("split-bf16 negdist full size")
+    r = run_gpu("negdist", x, y, w, wl.P, seed=wl.dir_seed, precision="split_bf16")
+    ref = oracle_s("negdist", x, y, w, r["xi"])
+    err = sliced.rel_l2(r["s"], ref)
+    note(f"  rel err vs oracle {err:.3e}")
+    assert err <= MIXED_TOL
+
+
+def test_split_bf16_gauss_ndft_workload_f64_input():
+    wl = wlm.WORKLOADS["gauss_ndft"]
+    x, y, w = wlm.generate(wl)
+    sigma = wlm.median_heuristic(x, y)
+    note("split-bf16 gauss_ndft full size")
+    r = run_gpu("gaussian", x, y, w, wl.P, seed=wl.dir_seed, sigma=sigma, n_coeff=wl.n_coeff, T=wl.T,
+                method="ndft", precision="split_bf16")
+    ref = oracle_s("gaussian", x, y, w, r["xi"], sigma, "ndft", wl.n_coeff, wl.T)
+    err = sliced.rel_l2(r["s"], ref)
+    note(f"  rel err vs oracle {err:.3e}")
+    assert err <= MIXED_TOL
+
+
+def test_split_bf16_gauss_nfft_workload_reduced():
+    wl = wlm.scaled(wlm.WORKLOADS["gauss_nfft"], N=20000, M=15000, P=6)
+    x, y, w = wlm.generate(wl)
+    sigma = wlm.median_heuristic(x, y)
+    note("split-bf16 gauss_nfft reduced")
+    r = run_gpu("gaussian", x, y, w, wl.P, seed=wl.dir_seed, sigma=sigma, n_coeff=wl.n_coeff, T=wl.T,
+                method="nfft", oversample=2, window_m=6, precision="split_bf16")
+    ref = oracle_s("gaussian", x, y, w, r["xi"], sigma, "nfft", wl.n_coeff, wl.T)
+    err = sliced.rel_l2(r["s"], ref)
+    note(f"  rel err vs oracle {err:.3e}")
+    assert err <= MIXED_TOL
+
+
+def test_split_bf16_laplace_workload_reduced():
+    wl = wlm.scaled(wlm.WORKLOADS["laplace"], N=4000, M=3000, P=6)
+    x, y, w = wlm.generate(wl)
+    sigma = wlm.median_heuristic(x, y)
+    note("split-bf16 laplace reduced")
+    r = run_gpu("laplacian", x, y, w, wl.P, seed=wl.dir_seed, sigma=sigma, n_coeff=wl.n_coeff, T=wl.T,
+                probe=True, precision="split_bf16")
+    _check_perm(r["z"], r["perm"])
+    ref = oracle_s("laplacian", x, y, w, r["xi"], sigma, "nfft", wl.n_coeff, wl.T)
+    err = sliced.rel_l2(r["s"], ref)
+    note(f"  rel err vs oracle {err:.3e}")
+    assert err <= MIXED_TOL

@@ -65,7 +65,7 @@ def test_validation_status_codes():
     assert _st(10, 4, G, method="sort") == ks.KSUM_EUNSUPPORTED
     assert _st(10, 4, N, method="nfft") == ks.KSUM_EUNSUPPORTED
     assert _st(10, 4, N, sigma=0.0) == ks.KSUM_OK               # sigma unused by the negative distance
-    assert _st(10, 4, G, precision=1) == ks.KSUM_EUNSUPPORTED
+    assert _st(10, 4, G, precision=1) == ks.KSUM_OK
     assert _st(10, 4, G, precision=5) == ks.KSUM_EINVAL
     assert _st(10, 4, G, slice_batch=-1) == ks.KSUM_EINVAL
     assert _st(10, 4, G, method="nfft", n_coeff=128, oversample=3) == ks.KSUM_EUNSUPPORTED   # grid not 2^k
