@@ -16,9 +16,12 @@ Modules
   sliced      Algorithm "alg:fast_Fourier_sliced" with the rescaling of Sec. 3.1
               and the Laplacian decomposition of Sec. 3.3
   direct      the exact O(MN) kernel sum (problem statement, Sec. 1 / Sec. 3)
+  gradient    gradients of the sliced fast sum: derivative sums by Fourier
+              summation with 2 pi i k c_k and by sorting (sign(0) = 0), and the
+              back-projection onto the directions
 
 Every floating-point computation is FP64.  Pinned by tests/test_oracle_*.py
 against closed forms, independent library evaluations (mpmath), brute force on
 tiny inputs, exactness on small integers and the O(P^-1/2) slicing rate.
 """
-from . import directions, kernels, onedim, sliced, direct  # noqa: F401
+from . import directions, kernels, onedim, sliced, direct, gradient  # noqa: F401
