@@ -206,6 +206,34 @@ ksum_status ksum_execute_probe_f64in(ksum_plan *plan, const double *x, int64_t N
                                      const double *w, float *s, void *ws, size_t ws_bytes, void *stream,
                                      const ksum_probe *probe);
 
+/* Workspace bytes ksum_backward needs for N sources and M targets. */
+ksum_status ksum_backward_workspace_size(const ksum_plan *plan, int64_t N, int64_t M, size_t *bytes);
+
+/* Gradients of a loss L through the forward sum s = ksum_execute(plan, x, y, w), given
+ * grad_s = dL/ds (device float[M]).  With the directions held fixed, the chain rule
+ * through the projections of Algorithm "Sliced Fast Fourier Summation" gives
+ *   grad_w[n]    = (1/P) sum_p sum_m grad_s[m] k(<xi_p,x_n>, <xi_p,y_m>)   (the forward sum with
+ *                  sources y weighted by grad_s and targets x)
+ *   grad_y[m][.] = grad_s[m]/P sum_p D^y[m][p] xi_p,  D^y[m][p] = d/dz sum_n w_n f(|<xi_p,x_n> - z|) at
+ *                  z = <xi_p,y_m>
+ *   grad_x[n][.] = w[n]/P sum_p D^x[n][p] xi_p,       D^x[n][p] = d/dz sum_m grad_s[m] f(|<xi_p,y_m> - z|)
+ *                  at z = <xi_p,x_n>
+ * The derivative sums come from the same 1-D methods as the forward sums: Fourier
+ * summation (Sec. 3.1) with the coefficients c_k times 2 pi i k, and the sorted
+ * prefix sums of Sec. 3.2 with sign(0) = 0 (a source at the target's position adds
+ * nothing); the rescaling bounds and tau are held constant.
+ *   x, y, w       the forward inputs (device float, layouts as in ksum_execute)
+ *   grad_s        device float[M]
+ *   grad_x        device float[N][d] output, or NULL to skip
+ *   grad_y        device float[M][d] output, or NULL to skip
+ *   grad_w        device float[N] output, or NULL to skip
+ *   ws            device workspace of ws_bytes >= ksum_backward_workspace_size(plan, N, M)
+ * Outputs are overwritten; none may overlap an input or the workspace.  Errors as
+ * for ksum_execute. */
+ksum_status ksum_backward(ksum_plan *plan, const float *x, int64_t N, const float *y, int64_t M, const float *w,
+                          const float *grad_s, float *grad_x, float *grad_y, float *grad_w, void *ws,
+                          size_t ws_bytes, void *stream);
+
 /* Per-kernel timing (diagnostic).  While enabled, ksum_execute records HIP events
  * on its stream around every kernel it launches (a few microseconds of overhead
  * per kernel); ksum_stage_times synchronises with the last event and returns,

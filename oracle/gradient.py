@@ -93,19 +93,31 @@ def sliced_grad(kernel: str, x, y, w, g, xi, sigma: float = 1.0, method: str = "
     w = np.asarray(w, dtype=np.float64)
     g = np.asarray(g, dtype=np.float64)
     xi = np.asarray(xi, dtype=np.float64)
-    d = x.shape[1]
-    P = xi.shape[0]
     zx = sliced.project(x, xi)
     zy = sliced.project(y, xi)
-    Dy = np.empty((y.shape[0], P))
-    Dx = np.empty((x.shape[0], P))
+    gx, gy = grad_from_projections(kernel, x.shape[1], zx, zy, w, g, xi, sigma, method, n_coeff, T)
+    grad_w = sliced.sliced_sum(kernel, y, x, g, xi, sigma, method, n_coeff, T)
+    return gx, gy, grad_w
+
+
+def grad_from_projections(kernel: str, d: int, zx, zy, w, g, xi, sigma: float = 1.0, method: str = "sort",
+                          n_coeff: int = 0, T: float = 0.0):
+    """(dL/dx, dL/dy) from given projections zx (N, P) and zy (M, P): the derivative sums of
+    every slice and the back-projection onto the directions xi (P, d)."""
+    zx = np.asarray(zx, dtype=np.float64)
+    zy = np.asarray(zy, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    xi = np.asarray(xi, dtype=np.float64)
+    P = xi.shape[0]
+    Dy = np.empty((zy.shape[0], P))
+    Dx = np.empty((zx.shape[0], P))
     for p in range(P):
         Dy[:, p] = slice_deriv(kernel, d, zx[:, p], zy[:, p], w, sigma, method, n_coeff, T)
         Dx[:, p] = slice_deriv(kernel, d, zy[:, p], zx[:, p], g, sigma, method, n_coeff, T)
     grad_y = (g / P)[:, None] * (Dy @ xi)
     grad_x = (w / P)[:, None] * (Dx @ xi)
-    grad_w = sliced.sliced_sum(kernel, y, x, g, xi, sigma, method, n_coeff, T)
-    return grad_x, grad_y, grad_w
+    return grad_x, grad_y
 
 
 def direct_deriv_1d(zx, zy, w, f, h: float = 1e-5):

@@ -69,6 +69,10 @@ _sigs = {
                                           _P, ctypes.POINTER(ksum_probe)]),
     "ksum_execute_probe_f64in": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P,
                                                 ctypes.c_size_t, _P, ctypes.POINTER(ksum_probe)]),
+    "ksum_backward_workspace_size": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64,
+                                                    ctypes.POINTER(ctypes.c_size_t)]),
+    "ksum_backward": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P, _P, _P, _P,
+                                     ctypes.c_size_t, _P]),
     "ksum_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ksum_stage_times": (ctypes.c_int, [_P, _P, _P]),
     "ksum_stage_count": (ctypes.c_int32, []),
@@ -196,6 +200,18 @@ def ksum_execute_probe_f64in(plan: int, x: int, N: int, y: int, M: int, w: int, 
            "ksum_execute_probe_f64in")
 
 
+def ksum_backward_workspace_size(plan: int, N: int, M: int) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.ksum_backward_workspace_size(plan, N, M, ctypes.byref(out)), "ksum_backward_workspace_size")
+    return out.value
+
+
+def ksum_backward(plan: int, x: int, N: int, y: int, M: int, w: int, grad_s: int, grad_x: Optional[int],
+                  grad_y: Optional[int], grad_w: Optional[int], ws: int, ws_bytes: int, stream: int) -> None:
+    _check(_lib.ksum_backward(plan, x, N, y, M, w, grad_s, grad_x, grad_y, grad_w, ws, ws_bytes, stream),
+           "ksum_backward")
+
+
 def ksum_set_timing(plan: int, enable: bool) -> None:
     _check(_lib.ksum_set_timing(plan, 1 if enable else 0), "ksum_set_timing")
 
@@ -235,6 +251,7 @@ class Plan:
         self.params = make_params(self.kid, directions=directions, **params)
         self.handle = ksum_plan_create(self.d, self.P, self.kid, self.params)
         self._ws = None
+        self._bws = None
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -283,3 +300,58 @@ class Plan:
             ksum_execute(self.handle, x.data_ptr(), N, y.data_ptr(), M, w.data_ptr(), s.data_ptr(),
                          ws.data_ptr(), ws.numel(), st)
         return s
+
+    def backward(self, x, y, w, grad_s, need_x: bool = True, need_y: bool = True, need_w: bool = True,
+                 stream=None):
+        """(grad_x, grad_y, grad_w) of a loss with dL/ds = grad_s (FP32 tensors; None where not needed)."""
+        import torch
+        N, M = x.shape[0], y.shape[0]
+        for t in (x, y, w, grad_s):
+            if t.dtype != torch.float32 or not t.is_cuda:
+                raise TypeError("backward takes FP32 GPU tensors")
+        if x.shape[1] != self.d or y.shape[1] != self.d or w.shape[0] != N or grad_s.shape[0] != M:
+            raise ValueError("shape mismatch")
+        x, y, w, grad_s = x.contiguous(), y.contiguous(), w.contiguous(), grad_s.contiguous()
+        need = ksum_backward_workspace_size(self.handle, N, M)
+        if self._bws is None or self._bws.numel() < need or self._bws.device != x.device:
+            self._bws = torch.empty(max(need, 256), dtype=torch.uint8, device=x.device)
+        gx = torch.empty((N, self.d), dtype=torch.float32, device=x.device) if need_x else None
+        gy = torch.empty((M, self.d), dtype=torch.float32, device=x.device) if need_y else None
+        gw = torch.empty(N, dtype=torch.float32, device=x.device) if need_w else None
+        st = (stream if stream is not None else torch.cuda.current_stream(x.device)).cuda_stream
+        ksum_backward(self.handle, x.data_ptr(), N, y.data_ptr(), M, w.data_ptr(), grad_s.data_ptr(),
+                      gx.data_ptr() if gx is not None else None, gy.data_ptr() if gy is not None else None,
+                      gw.data_ptr() if gw is not None else None, self._bws.data_ptr(), self._bws.numel(), st)
+        return gx, gy, gw
+
+
+def _make_autograd():
+    import torch
+
+    class KernelSum(torch.autograd.Function):
+        """s = KernelSum.apply(plan, x, y, w): the sliced kernel sum with a hand-written backward
+        (ksum_backward) for gradients with respect to x, y and w."""
+
+        @staticmethod
+        def forward(ctx, plan, x, y, w):
+            ctx.plan = plan
+            ctx.save_for_backward(x, y, w)
+            return plan(x.detach(), y.detach(), w.detach())
+
+        @staticmethod
+        def backward(ctx, grad_s):
+            x, y, w = ctx.saved_tensors
+            gx, gy, gw = ctx.plan.backward(x.detach(), y.detach(), w.detach(), grad_s.detach().float(),
+                                           need_x=ctx.needs_input_grad[1], need_y=ctx.needs_input_grad[2],
+                                           need_w=ctx.needs_input_grad[3])
+            return None, gx, gy, gw
+
+    return KernelSum
+
+
+def __getattr__(name):
+    if name == "KernelSum":
+        cls = _make_autograd()
+        globals()["KernelSum"] = cls
+        return cls
+    raise AttributeError(name)

@@ -21,7 +21,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 # gfx950 only; packed FP32 instructions are disabled for every HIP file
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 SOURCES = ["ksum_api.cpp", "host_tables.cpp", "k_project.hip", "k_setup.hip", "k_sort.hip",
-           "k_fourier.hip", "k_reduce.hip", "k_project_bf16.hip"]
+           "k_fourier.hip", "k_reduce.hip", "k_project_bf16.hip", "k_backproj.hip"]
 
 
 def _compile(src: str) -> str:

@@ -88,6 +88,8 @@ struct ksum_plan {
   float *d_dirs = nullptr;       // [P_pad][d_pad] FP32, zero padded
   uint16_t *d_dirs_hi = nullptr; // [P_pad][d_pad] bf16 hi half of the FP32 directions (split-BF16)
   uint16_t *d_dirs_lo = nullptr; // [P_pad][d_pad] bf16 lo half (split-BF16)
+  float *d_dirsT = nullptr;      // [d][Pk] FP32 transposed directions (backward), Pk = P rounded up to 16
+  int32_t Pk = 0;
   float *d_deconv = nullptr;     // [K+1] 1 / (n phihat(k))^2 (NFFT)
   float2 *d_twiddle = nullptr;   // [n_grid] exp(-2 pi i j / n)
   double *d_costab = nullptr;    // [lap_L] cos(2 pi j / lap_L)
@@ -156,6 +158,9 @@ struct ExecArgs {
   bool want_perm;         // order ties by union index
   int32_t *perm_out;      // [P][L] or null
   float *t_out;           // [P][M] or null (probe)
+  bool deriv;             // derivative sums instead of sums (backward)
+  float *dout;            // derivative mode: [M][ldd] per-target, per-slice derivative sums
+  int64_t ldd;
 };
 
 template <typename T> inline T *wsp(const ExecArgs &a, size_t off) {
@@ -182,6 +187,10 @@ hipError_t launch_nfft(const ExecArgs &a);
 hipError_t launch_sort_path(const ExecArgs &a);
 hipError_t launch_accumulate(const ExecArgs &a, float *s, bool first, bool last);
 hipError_t launch_nfft_interp(const ExecArgs &a, float *s, bool first, bool last);
+hipError_t launch_deriv_gather(const ExecArgs &a);
+hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t stream);
+hipError_t launch_backproject(const ksum_plan &plan, const float *D, int64_t ldd, int64_t R, const float *scale,
+                              double factor, float *out, hipStream_t stream);
 
 // host tables
 void generate_directions(int32_t d, int32_t P, uint64_t seed, double *out);

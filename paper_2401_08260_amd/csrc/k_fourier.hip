@@ -46,6 +46,7 @@ struct FourierArgs {
   int32_t i0min, i0max;    // clamp of the base cell
   const float2 *twiddle;   // [n]
   WindowPoly poly;
+  int32_t deriv;           // derivative sums (coefficients times 2 pi i k, result times tau)
 };
 
 __global__ __launch_bounds__(256) void ndft_adjoint_kernel(FourierArgs a) {
@@ -118,13 +119,23 @@ __global__ __launch_bounds__(256) void ndft_forward_kernel(FourierArgs a, int yc
   for (int64_t m = m0 + threadIdx.x; m < m1; m += blockDim.x) {
     const float yt = (Zy[m] - sp.fcmin) * sp.ftau + sp.shift;
     float acc = 0.f;
-    for (int k = 0; k <= a.K; ++k) {
-      float s, co;
-      sincospif(2.0f * (float)k * yt, &s, &co);
-      // Re((hr + i hi)(cos + i sin)) = hr cos - hi sin
-      acc += h[k].x * co - h[k].y * s;
+    if (a.deriv) {
+      // d/dy~ Re((hr + i hi) exp(2 pi i k y~)) = -2 pi k (hr sin + hi cos); times tau = dy~/dz
+      for (int k = 1; k <= a.K; ++k) {
+        float s, co;
+        sincospif(2.0f * (float)k * yt, &s, &co);
+        acc += (float)k * (h[k].x * s + h[k].y * co);
+      }
+      tp[m] = -6.283185307179586f * sp.ftau * acc;
+    } else {
+      for (int k = 0; k <= a.K; ++k) {
+        float s, co;
+        sincospif(2.0f * (float)k * yt, &s, &co);
+        // Re((hr + i hi)(cos + i sin)) = hr cos - hi sin
+        acc += h[k].x * co - h[k].y * s;
+      }
+      tp[m] = acc;
     }
-    tp[m] = acc;
   }
 }
 
@@ -144,6 +155,7 @@ hipError_t launch_ndft(const ExecArgs &a) {
   f.coef = wsp<float>(a, lay.off_coef);
   f.part = wsp<float2>(a, lay.off_fpart);
   f.t = wsp<float>(a, lay.off_t1);
+  f.deriv = a.deriv ? 1 : 0;
   mark(a, ST_NDFT_ADJOINT);
   ndft_adjoint_kernel<<<(unsigned)xcd_grid((int64_t)a.nsl * f.chunks), 256, 0, a.stream>>>(f);
   const int ychunk = 2048;
@@ -263,7 +275,13 @@ __global__ __launch_bounds__(256) void nfft_grid_kernel(FourierArgs a) {
     const int k = (j < n / 2) ? j : j - n;
     const int ak = k < 0 ? -k : k;
     const float f = (ak <= a.K) ? cf[ak] : 0.f;
-    x[j] = make_float2(x[j].x * f, x[j].y * f);
+    if (a.deriv) {
+      // times 2 pi i k: the inverse transform is then the derivative in y~
+      const float c = 6.283185307179586f * (float)k * f;
+      x[j] = make_float2(-x[j].y * c, x[j].x * c);
+    } else {
+      x[j] = make_float2(x[j].x * f, x[j].y * f);
+    }
   }
   __syncthreads();
   // inverse FFT: G_l = sum_k h_k exp(+2 pi i k l / n)
@@ -302,6 +320,9 @@ struct AccumArgs {
   int first, last;
   double invP;
   int tpt;                // targets per thread
+  float *dout;            // derivative mode: dout[m * ldd + p0 + p] = tau t'(y~) + t2, no average
+  int64_t ldd;
+  int p0;
 };
 
 template <int MW, int DEG>
@@ -340,13 +361,16 @@ __global__ __launch_bounds__(256) void nfft_interp_accum_kernel(FourierArgs a, A
           float tv = 0.f;
 #pragma unroll
           for (int j = 0; j < 2 * MW; ++j) tv = fmaf(gb[j], tap[j], tv);
+          if (c.dout) tv *= sp.ftau;
           if (c.t2) tv += c.t2[(int64_t)p * a.M + m];
           if (c.t_out) c.t_out[(int64_t)p * a.M + m] = tv;
+          if (c.dout) c.dout[m * c.ldd + c.p0 + p] = tv;
           acc[k] += (double)tv;
         }
       }
     }
   }
+  if (c.dout) return;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (k >= c.tpt) break;
@@ -419,6 +443,7 @@ static FourierArgs nfft_args(const ExecArgs &a) {
   f.i0max = lay.win_lo + lay.win_cells - 1 - m;
   f.twiddle = pl.d_twiddle;
   f.poly = pl.poly;
+  f.deriv = a.deriv ? 1 : 0;
   return f;
 }
 
@@ -459,6 +484,9 @@ hipError_t launch_nfft_interp(const ExecArgs &a, float *s, bool first, bool last
   c.last = last ? 1 : 0;
   c.invP = 1.0 / (double)pl.P;
   c.tpt = (int)std::max<int64_t>(1, std::min<int64_t>(4, lay.M / (256 * 1024)));
+  c.dout = a.deriv ? a.dout : nullptr;
+  c.ldd = a.ldd;
+  c.p0 = a.p0;
   switch (pl.params.window_m) {
     case 2: launch_interp_m<2, 9>(f, c, a); break;
     case 3: launch_interp_m<3, 9>(f, c, a); break;

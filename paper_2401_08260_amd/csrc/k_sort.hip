@@ -26,6 +26,12 @@
 //               global memory with the same ranking.
 // The order produced is the stable ascending order of the FP32 projections
 // (ties by union index), i.e. the permutation sigma of Sec. 3.2.
+//
+// Derivative mode (gradients): the emitted value is d/dz_m of the sum,
+// -c' (A_< - A_>) with strict inequalities (sign(0) = 0).  Targets have the lower
+// union indices, so inside a run of equal keys they come before the sources:
+// the exclusive prefix at a target is A_<, and A_> = A_tot - A_<= needs the sum
+// A_= of the sources tied with it: D = -c' (2 A_< + A_= - A_tot).
 #include <algorithm>
 
 #include "device_common.h"
@@ -53,6 +59,7 @@ struct SortArgs {
   uint32_t *fail_count; // groups handed to the fallback kernel (zeroed by the scan kernel)
   uint32_t *fail_list;  // [nsl * G] work items
   int4 *desc;           // [nsl][G] (first bucket, first entry, end entry, 0) of each group
+  int32_t deriv;        // 0: t = the sums; 1: t = their derivatives at the targets
 };
 
 __device__ __forceinline__ int bucket_of(float z, float fcmin, float invw, int nb) {
@@ -458,6 +465,111 @@ __device__ __forceinline__ void scan_emit(const SortArgs &a, int p, const SliceP
   cS += totS;
 }
 
+// Derivative emission (see the top of the file) for a group sorted in LDS: the
+// exclusive fixed-point prefixes of the weights go to the free LDS buffers (low and
+// high 32 bits), and the end of each target's run of equal keys is found by binary
+// search in the sorted keys; D = -c' (E_i + E_end - A_tot).
+__device__ void deriv_emit_lds(const SortArgs &a, int p, int eA, const uint32_t *K, const uint32_t *I,
+                               uint32_t *Elo, uint32_t *Ehi, int n, int64_t out_pos, long long cA, long long Atot,
+                               long long *sm) {
+  constexpr int per = kSortCap / 256;
+  const int i0 = threadIdx.x * per;
+  long long fa[per];
+  long long lA = 0;
+#pragma unroll
+  for (int q = 0; q < per; ++q) {
+    const int i = i0 + q;
+    fa[q] = (i < n && (int64_t)I[i] >= a.M) ? fix_a(a.w[I[i] - a.M], eA) : 0;
+    lA += fa[q];
+  }
+  long long tot;
+  long long ex = block_exclusive_scan(lA, sm, &tot) + cA;
+#pragma unroll
+  for (int q = 0; q < per; ++q) {
+    const int i = i0 + q;
+    if (i < n) {
+      Elo[i] = (uint32_t)ex;
+      Ehi[i] = (uint32_t)((unsigned long long)ex >> 32);
+    }
+    ex += fa[q];
+  }
+  __syncthreads();
+  const long long endA = cA + tot;
+  const double sa = ldexp(1.0, -eA);
+  float *tp = a.t + (int64_t)p * a.M;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint32_t idx = I[i];
+    if (a.perm) a.perm[(int64_t)p * a.L + out_pos + i] = (int32_t)idx;
+    if ((int64_t)idx < a.M) {
+      const uint32_t k = K[i];
+      int lo = i + 1, hi = n;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (K[mid] <= k) lo = mid + 1; else hi = mid;
+      }
+      const long long Ei = (long long)(((unsigned long long)Ehi[i] << 32) | Elo[i]);
+      const long long Eb = (lo < n) ? (long long)(((unsigned long long)Ehi[lo] << 32) | Elo[lo]) : endA;
+      tp[idx] = (float)(-a.cneg * ((double)(Ei + Eb - Atot) * sa));
+    }
+  }
+  __syncthreads();
+}
+
+// The same for a large group sorted in global memory (src, n entries): the prefixes
+// go to the free buffer dst in a first pass over LDS tiles.
+__device__ void deriv_emit_stream(const SortArgs &a, GroupShared &g, int p, int eA,
+                                  const unsigned long long *src, unsigned long long *dst, int64_t n,
+                                  int64_t out_pos, long long cA, long long Atot) {
+  constexpr int per = kSortCap / 256;
+  long long *E = reinterpret_cast<long long *>(dst);
+  long long carry = cA;
+  for (int64_t t0 = 0; t0 < n; t0 += kSortCap) {
+    const int tn = (int)min((int64_t)kSortCap, n - t0);
+    const int i0 = threadIdx.x * per;
+    long long fa[per];
+    long long lA = 0;
+#pragma unroll
+    for (int q = 0; q < per; ++q) {
+      const int i = i0 + q;
+      fa[q] = 0;
+      if (i < tn) {
+        const uint32_t idx = (uint32_t)(src[t0 + i] >> 32);
+        if ((int64_t)idx >= a.M) fa[q] = fix_a(a.w[idx - a.M], eA);
+      }
+      lA += fa[q];
+    }
+    long long tot;
+    long long ex = block_exclusive_scan(lA, g.rs.sm, &tot) + carry;
+#pragma unroll
+    for (int q = 0; q < per; ++q) {
+      const int i = i0 + q;
+      if (i < tn) E[t0 + i] = ex;
+      ex += fa[q];
+    }
+    carry += tot;
+    __syncthreads();
+  }
+  const long long endA = carry;
+  const double sa = ldexp(1.0, -eA);
+  float *tp = a.t + (int64_t)p * a.M;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const unsigned long long e = src[i];
+    const uint32_t idx = (uint32_t)(e >> 32);
+    if (a.perm) a.perm[(int64_t)p * a.L + out_pos + i] = (int32_t)idx;
+    if ((int64_t)idx < a.M) {
+      const uint32_t k = (uint32_t)e;
+      int64_t lo = i + 1, hi = n;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((uint32_t)src[mid] <= k) lo = mid + 1; else hi = mid;
+      }
+      const long long Eb = (lo < n) ? E[lo] : endA;
+      tp[idx] = (float)(-a.cneg * ((double)(E[i] + Eb - Atot) * sa));
+    }
+  }
+  __syncthreads();
+}
+
 // Sort the tile's equal-key runs by union index.  Returns false if a run is
 // longer than 32 (then the caller re-sorts the whole tile by (key, index)).
 __device__ __forceinline__ bool fix_ties(uint32_t *K, uint32_t *I, int n, uint32_t *flag) {
@@ -600,7 +712,10 @@ __device__ void fallback_group(const SortArgs &a, GroupShared &g, int64_t item) 
         cur ^= 1;
       }
     }
-    scan_emit<nopad>(a, p, sp, eA, g.K[cur], g.I[cur], nullptr, nn, e_lo, cA, cS, Atot, Stot, g.rs.sm);
+    if (a.deriv)
+      deriv_emit_lds(a, p, eA, g.K[cur], g.I[cur], g.K[cur ^ 1], g.I[cur ^ 1], nn, e_lo, cA, Atot, g.rs.sm);
+    else
+      scan_emit<nopad>(a, p, sp, eA, g.K[cur], g.I[cur], nullptr, nn, e_lo, cA, cS, Atot, Stot, g.rs.sm);
     return;
   }
 
@@ -645,6 +760,10 @@ __device__ void fallback_group(const SortArgs &a, GroupShared &g, int64_t item) 
   for (int sh = 0; sh < kbits; sh += 8) {
     stream_pass(g, src, dst, n, [=](uint32_t k, uint32_t) { return ((k - kmin) >> sh) & 255u; });
     unsigned long long *tmp = src; src = dst; dst = tmp;
+  }
+  if (a.deriv) {
+    deriv_emit_stream(a, g, p, eA, src, dst, n, e_lo, cA, Atot);
+    return;
   }
   for (int64_t t0 = 0; t0 < n; t0 += kSortCap) {
     const int tn = (int)min((int64_t)kSortCap, n - t0);
@@ -730,7 +849,7 @@ __device__ __forceinline__ void scan_emit_fast(const SortArgs &a, int p, const S
   const int i0 = threadIdx.x * kFPer;
   const double sa = ldexp(1.0, -eA), ss = ldexp(1.0, -sp.eS);
   uint32_t kk[kFPer], ii[kFPer];
-  float ww[kFPer];
+  float ww[kFPer], eqw[kFPer];
   double lA = 0.0, lS = 0.0;
 #pragma unroll
   for (int q = 0; q < kFPer; ++q) {
@@ -738,11 +857,13 @@ __device__ __forceinline__ void scan_emit_fast(const SortArgs &a, int p, const S
     kk[q] = 0;
     ii[q] = 0;
     ww[q] = 0.f;
+    eqw[q] = 0.f;
     if (j < n) {
       const int e = pad8(f.inv[pad8(j)]);
       kk[q] = f.K[e];
       ii[q] = f.I[e];
-      ww[q] = f.W[e];
+      ww[q] = ((int64_t)ii[q] >= a.M) ? f.W[e] : 0.f;
+      if (a.deriv && (int64_t)ii[q] < a.M) eqw[q] = f.W[e];
       lA += (double)ww[q];
       lS += (double)ww[q] * ((double)key_float(kk[q]) - sp.cmid);
     }
@@ -757,8 +878,12 @@ __device__ __forceinline__ void scan_emit_fast(const SortArgs &a, int p, const S
     const int j = i0 + q;
     if (j < n) {
       const double zb = (double)key_float(kk[q]) - sp.cmid;
-      if ((int64_t)ii[q] < a.M)
-        tp[ii[q]] = (float)(-a.cneg * (zb * (2.0 * exA - totAd) - (2.0 * exS - totSd)));
+      if ((int64_t)ii[q] < a.M) {
+        if (a.deriv)
+          tp[ii[q]] = (float)(-a.cneg * (2.0 * exA + (double)eqw[q] - totAd));
+        else
+          tp[ii[q]] = (float)(-a.cneg * (zb * (2.0 * exA - totAd) - (2.0 * exS - totSd)));
+      }
       if (a.perm) a.perm[(int64_t)p * a.L + out_pos + j] = (int32_t)ii[q];
       exA += (double)ww[q];
       exS += (double)ww[q] * zb;
@@ -892,6 +1017,13 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
           const unsigned long long v = ((unsigned long long)kk << 32) | ii;
           for (int j = b; j < e; ++j)
             rank += ((((unsigned long long)f.K[pad8(j)] << 32) | f.I[pad8(j)]) < v) ? 1 : 0;
+          if (a.deriv && (int64_t)ii < a.M) {
+            // sources tied with this target; kept in the target's (otherwise zero) weight slot
+            float eq = 0.f;
+            for (int j = b; j < e; ++j)
+              if (f.K[pad8(j)] == kk && (int64_t)f.I[pad8(j)] >= a.M) eq += f.W[pad8(j)];
+            f.W[pad8(i)] = eq;
+          }
         }
         f.inv[pad8(min(b + rank, kSortCap - 1))] = (uint16_t)i;
       }
@@ -935,6 +1067,7 @@ hipError_t launch_sort_path(const ExecArgs &a) {
   s.t = wsp<float>(a, pl.kernel == KSUM_LAPLACIAN ? lay.off_t2 : lay.off_t1);
   s.perm = a.perm_out ? a.perm_out + (int64_t)a.p0 * lay.L : nullptr;
   s.cneg = pl.sort_const;
+  s.deriv = a.deriv ? 1 : 0;
   const unsigned g1 = (unsigned)xcd_grid((int64_t)a.nsl * kSortChunks);
   mark(a, ST_SORT_HIST);
   sort_hist_kernel<<<g1, 512, 0, a.stream>>>(s);

@@ -200,6 +200,7 @@ static void free_plan(ksum_plan *pl) {
   free_timer(pl);
   if (pl->d_dirs) (void)hipFree(pl->d_dirs);
   if (pl->d_dirs_hi) (void)hipFree(pl->d_dirs_hi);
+  if (pl->d_dirsT) (void)hipFree(pl->d_dirsT);
   if (pl->d_dirs_lo) (void)hipFree(pl->d_dirs_lo);
   if (pl->d_deconv) (void)hipFree(pl->d_deconv);
   if (pl->d_twiddle) (void)hipFree(pl->d_twiddle);
@@ -269,6 +270,7 @@ static ksum_status plan_host_setup(int32_t d, int32_t P, ksum_kernel kernel, con
   pl->use_fourier = (kernel != KSUM_NEGDIST);
   pl->d_pad = (int32_t)((d + kGemmBK - 1) / kGemmBK * kGemmBK);
   pl->P_pad = (int32_t)((P + kGemmBM - 1) / kGemmBM * kGemmBM + kGemmBM);
+  pl->Pk = (int32_t)((P + kGemmBK - 1) / kGemmBK * kGemmBK);
   pl->cd = std::sqrt(M_PI) * std::exp(std::lgamma((d + 1) / 2.0) - std::lgamma(d / 2.0));
   pl->sort_const = (kernel == KSUM_LAPLACIAN) ? pl->cd / p.sigma : pl->cd;
   pl->gauss_logc = std::log((double)d * M_PI / std::sqrt(2.0)) - std::lgamma((d + 2) / 2.0);
@@ -340,6 +342,15 @@ ksum_status ksum_plan_create(int32_t d, int32_t P, ksum_kernel kernel, const ksu
   if (hipMalloc(&pl->d_dirs, hd.size() * sizeof(float)) != hipSuccess) return dev_fail(KSUM_ENOMEM, "hipMalloc");
   if (hipMemcpy(pl->d_dirs, hd.data(), hd.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
     return dev_fail(KSUM_EDEVICE, "hipMemcpy");
+  {
+    // transposed FP32 directions [d][Pk] for the back-projection of the backward pass
+    std::vector<float> ht((size_t)d * pl->Pk, 0.f);
+    for (int32_t p = 0; p < P; ++p)
+      for (int32_t i = 0; i < d; ++i) ht[(size_t)i * pl->Pk + p] = (float)pl->dirs[(size_t)p * d + i];
+    if (hipMalloc(&pl->d_dirsT, ht.size() * sizeof(float)) != hipSuccess) return dev_fail(KSUM_ENOMEM, "hipMalloc");
+    if (hipMemcpy(pl->d_dirsT, ht.data(), ht.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+      return dev_fail(KSUM_EDEVICE, "hipMemcpy");
+  }
   if (pl->params.precision == KSUM_SPLIT_BF16) {
     // hi = bf16(xi), lo = bf16(xi - hi) of the FP32 directions, round to nearest even
     std::vector<uint16_t> hh(hd.size()), hl(hd.size());
@@ -413,31 +424,25 @@ ksum_status ksum_workspace_size(const ksum_plan *plan, int64_t N, int64_t M, siz
   return KSUM_OK;
 }
 
-static ksum_status execute_impl(ksum_plan *plan, const void *x, int64_t N, const void *y, int64_t M,
-                                const void *w, bool f64, float *s, void *ws, size_t ws_bytes, void *stream,
-                                const ksum_probe *probe) {
-  if (!plan) return fail(KSUM_EINVAL, "plan is NULL");
-  if (!x || !y || !w || !s || !ws) return fail(KSUM_EINVAL, "null device pointer");
-  if (N < 1 || M < 1) return fail(KSUM_EINVAL, "N and M must be >= 1");
-  if (N + M > 0x7fffffffLL) return fail(KSUM_EUNSUPPORTED, "N + M must be < 2^31");
-  const Layout lay = make_layout(*plan, N, M);
-  if (ws_bytes < lay.total) return fail(KSUM_EWORKSPACE, "workspace too small");
-  if ((uintptr_t)ws % 256 != 0) return fail(KSUM_EINVAL, "workspace must be 256-byte aligned");
-  int prev = 0;
-  (void)hipGetDevice(&prev);
-  if (prev != plan->params.device && hipSetDevice(plan->params.device) != hipSuccess)
-    return fail(KSUM_EDEVICE, "hipSetDevice failed");
+// One pass of the hot path over all slices, batch by batch, on the plan's device:
+// forward sums into s, or (deriv) the per-target derivative sums into dout[M][ldd].
+static hipError_t run_pipeline(ksum_plan *plan, const Layout &lay, const void *x, const void *y, const void *w,
+                               bool f64, float *s, bool deriv, float *dout, int64_t ldd, char *ws,
+                               hipStream_t stream, const ksum_probe *probe) {
   ExecArgs a{};
   a.plan = plan;
   a.lay = &lay;
-  a.ws = static_cast<char *>(ws);
-  a.stream = static_cast<hipStream_t>(stream);
+  a.ws = ws;
+  a.stream = stream;
   a.x = x;
   a.y = y;
   a.f64in = f64;
   a.want_perm = probe && probe->perm;
   a.perm_out = probe ? probe->perm : nullptr;
   a.t_out = probe ? probe->t : nullptr;
+  a.deriv = deriv;
+  a.dout = dout;
+  a.ldd = ldd;
   a.w = f64 ? wsp<float>(a, lay.off_wf) : static_cast<const float *>(w);
   hipError_t e = launch_weight_prep(a, f64 ? static_cast<const double *>(w) : nullptr);
   for (int32_t p0 = 0; p0 < plan->P && e == hipSuccess; p0 += lay.B) {
@@ -453,14 +458,53 @@ static ksum_status execute_impl(ksum_plan *plan, const void *x, int64_t N, const
       e = (plan->method == KSUM_1D_NDFT) ? launch_ndft(a) : launch_nfft(a);
     if (e == hipSuccess && plan->use_sort) e = launch_sort_path(a);
     const bool first = p0 == 0, last = p0 + a.nsl >= plan->P;
-    if (e == hipSuccess)
-      e = (plan->use_fourier && plan->method == KSUM_1D_NFFT) ? launch_nfft_interp(a, s, first, last)
-                                                              : launch_accumulate(a, s, first, last);
+    const bool interp = plan->use_fourier && plan->method == KSUM_1D_NFFT;
+    if (e == hipSuccess) {
+      if (interp) e = launch_nfft_interp(a, s, first, last);
+      else if (deriv) e = launch_deriv_gather(a);
+      else e = launch_accumulate(a, s, first, last);
+    }
   }
   mark(a, -1);
+  return e;
+}
+
+static ksum_status check_exec_args(ksum_plan *plan, const void *x, int64_t N, const void *y, int64_t M,
+                                   const void *w, const void *ws) {
+  if (!plan) return fail(KSUM_EINVAL, "plan is NULL");
+  if (!x || !y || !w || !ws) return fail(KSUM_EINVAL, "null device pointer");
+  if (N < 1 || M < 1) return fail(KSUM_EINVAL, "N and M must be >= 1");
+  if (N + M > 0x7fffffffLL) return fail(KSUM_EUNSUPPORTED, "N + M must be < 2^31");
+  if ((uintptr_t)ws % 256 != 0) return fail(KSUM_EINVAL, "workspace must be 256-byte aligned");
+  return KSUM_OK;
+}
+
+static ksum_status execute_impl(ksum_plan *plan, const void *x, int64_t N, const void *y, int64_t M,
+                                const void *w, bool f64, float *s, void *ws, size_t ws_bytes, void *stream,
+                                const ksum_probe *probe) {
+  const ksum_status st = check_exec_args(plan, x, N, y, M, w, ws);
+  if (st != KSUM_OK) return st;
+  if (!s) return fail(KSUM_EINVAL, "null device pointer");
+  const Layout lay = make_layout(*plan, N, M);
+  if (ws_bytes < lay.total) return fail(KSUM_EWORKSPACE, "workspace too small");
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  if (prev != plan->params.device && hipSetDevice(plan->params.device) != hipSuccess)
+    return fail(KSUM_EDEVICE, "hipSetDevice failed");
+  const hipError_t e = run_pipeline(plan, lay, x, y, w, f64, s, false, nullptr, 0, static_cast<char *>(ws),
+                                    static_cast<hipStream_t>(stream), probe);
   if (prev != plan->params.device) (void)hipSetDevice(prev);
   if (e != hipSuccess) return fail(KSUM_EDEVICE, std::string("HIP launch failed: ") + hipGetErrorString(e));
   return KSUM_OK;
+}
+
+// Workspace of the backward pass: the larger of the two pipeline layouts (targets y
+// and targets x), then the derivative sums D [max(N, M)][Pk].
+static size_t backward_bytes(const ksum_plan &pl, int64_t N, int64_t M, size_t *d_off) {
+  const size_t a = make_layout(pl, N, M).total, b = make_layout(pl, M, N).total;
+  const size_t off = align_up(std::max(a, b), 256);
+  if (d_off) *d_off = off;
+  return off + (size_t)std::max(N, M) * pl.Pk * sizeof(float);
 }
 
 ksum_status ksum_execute(ksum_plan *plan, const float *x, int64_t N, const float *y, int64_t M, const float *w,
@@ -483,6 +527,56 @@ ksum_status ksum_execute_probe_f64in(ksum_plan *plan, const double *x, int64_t N
                                      const double *w, float *s, void *ws, size_t ws_bytes, void *stream,
                                      const ksum_probe *probe) {
   return execute_impl(plan, x, N, y, M, w, true, s, ws, ws_bytes, stream, probe);
+}
+
+ksum_status ksum_backward_workspace_size(const ksum_plan *plan, int64_t N, int64_t M, size_t *bytes) {
+  if (!plan || !bytes) return fail(KSUM_EINVAL, "null argument");
+  if (N < 1 || M < 1) return fail(KSUM_EINVAL, "N and M must be >= 1");
+  if (N + M > 0x7fffffffLL) return fail(KSUM_EUNSUPPORTED, "N + M must be < 2^31");
+  *bytes = backward_bytes(*plan, N, M, nullptr);
+  return KSUM_OK;
+}
+
+ksum_status ksum_backward(ksum_plan *plan, const float *x, int64_t N, const float *y, int64_t M, const float *w,
+                          const float *grad_s, float *grad_x, float *grad_y, float *grad_w, void *ws,
+                          size_t ws_bytes, void *stream) {
+  const ksum_status st = check_exec_args(plan, x, N, y, M, w, ws);
+  if (st != KSUM_OK) return st;
+  if (!grad_s) return fail(KSUM_EINVAL, "grad_s is NULL");
+  size_t d_off = 0;
+  if (ws_bytes < backward_bytes(*plan, N, M, &d_off)) return fail(KSUM_EWORKSPACE, "workspace too small");
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  if (prev != plan->params.device && hipSetDevice(plan->params.device) != hipSuccess)
+    return fail(KSUM_EDEVICE, "hipSetDevice failed");
+  char *wsc = static_cast<char *>(ws);
+  const hipStream_t sm = static_cast<hipStream_t>(stream);
+  float *D = reinterpret_cast<float *>(wsc + d_off);
+  const int64_t ldd = plan->Pk;
+  const double invP = 1.0 / (double)plan->P;
+  hipError_t e = hipSuccess;
+  // dL/dw: the sum with sources y (weights grad_s) and targets x
+  if (grad_w) {
+    const Layout lw = make_layout(*plan, M, N);
+    e = run_pipeline(plan, lw, y, x, grad_s, false, grad_w, false, nullptr, 0, wsc, sm, nullptr);
+  }
+  // dL/dy_m = grad_s_m / P * sum_p D^y[m][p] xi_p
+  if (e == hipSuccess && grad_y) {
+    const Layout ly = make_layout(*plan, N, M);
+    e = launch_fill_zero(D, M * ldd, sm);
+    if (e == hipSuccess) e = run_pipeline(plan, ly, x, y, w, false, nullptr, true, D, ldd, wsc, sm, nullptr);
+    if (e == hipSuccess) e = launch_backproject(*plan, D, ldd, M, grad_s, invP, grad_y, sm);
+  }
+  // dL/dx_n = w_n / P * sum_p D^x[n][p] xi_p, D^x with sources y (weights grad_s) and targets x
+  if (e == hipSuccess && grad_x) {
+    const Layout lx = make_layout(*plan, M, N);
+    e = launch_fill_zero(D, N * ldd, sm);
+    if (e == hipSuccess) e = run_pipeline(plan, lx, y, x, grad_s, false, nullptr, true, D, ldd, wsc, sm, nullptr);
+    if (e == hipSuccess) e = launch_backproject(*plan, D, ldd, N, w, invP, grad_x, sm);
+  }
+  if (prev != plan->params.device) (void)hipSetDevice(prev);
+  if (e != hipSuccess) return fail(KSUM_EDEVICE, std::string("HIP launch failed: ") + hipGetErrorString(e));
+  return KSUM_OK;
 }
 
 static const char *kStageNames[ST_COUNT] = {
