@@ -187,12 +187,180 @@ def cpu_baseline(wl, x, y, w, sigma, xi, s_gpu, t_gpu, budget_s, exact_targets, 
     return out, errs
 
 
+# ---------------------------------------------------------------------------
+# Serving mix: a Poisson stream of requests of uneven N, M, d, kernel and P.
+# ---------------------------------------------------------------------------
+SERVE_D = (16, 128, 784, 3072)
+MAX_PTS = 500_000
+
+
+def serve_params(kernel, sigma):
+    if kernel == "gaussian":
+        return dict(sigma=sigma, n_coeff=128, T=0.02, method="nfft", oversample=2, window_m=6)
+    if kernel == "laplacian":
+        return dict(sigma=sigma, n_coeff=256, T=0.125)
+    return {}
+
+
+def bench_serve(args):
+    """Replays the serving stream twice on one GPU and reports latency and throughput:
+      * served: the request server (continuous batching, `slots` concurrent streams,
+        admission by HBM footprint) with the split-BF16 projection;
+      * baseline: one request at a time in arrival order, FP32, on one stream.
+    Point sets live in HBM: per dimension and distribution one pool of 5e5 sources and
+    one of 5e5 targets, and each request takes a contiguous block of rows of each."""
+    import torch
+    import paper_2401_08260_amd as ks
+
+    reqs = wlm.serving_stream(args.serve_requests, args.serve_rate, seed=4)
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(4)
+    pools, sig = {}, {}
+    for d in SERVE_D:
+        for kind in ("normal", "uniform"):
+            mk = torch.randn if kind == "normal" else torch.rand
+            xs = mk((MAX_PTS, d), device=dev, generator=gen)
+            ys = mk((MAX_PTS, d), device=dev, generator=gen)
+            pools[(d, kind)] = (xs, ys)
+            sig[(d, kind)] = wlm.median_heuristic(xs[:250].cpu().numpy(), ys[:250].cpu().numpy())
+    wpool = torch.rand(MAX_PTS, device=dev, generator=gen)
+    gpool = torch.randn(MAX_PTS, device=dev, generator=gen)
+    rng = np.random.default_rng(5)
+    offs = [(int(rng.integers(0, MAX_PTS - r["N"] + 1)), int(rng.integers(0, MAX_PTS - r["M"] + 1))) for r in reqs]
+
+    def inputs(i):
+        r = reqs[i]
+        xs, ys = pools[(r["d"], r["data"])]
+        ox, oy = offs[i]
+        return xs[ox:ox + r["N"]], ys[oy:oy + r["M"]], wpool[:r["N"]], gpool[:r["M"]]
+
+    def params(i, precision):
+        r = reqs[i]
+        return dict(serve_params(r["kernel"], sig[(r["d"], r["data"])]), precision=precision, seed=r["P"])
+
+    def outputs(i):
+        r = reqs[i]
+        s = torch.empty(r["M"], device=dev)
+        gr = (None, None, None)
+        if r["grad"]:
+            gr = (torch.empty((r["N"], r["d"]), device=dev), torch.empty((r["M"], r["d"]), device=dev),
+                  torch.empty(r["N"], device=dev))
+        return s, gr
+
+    work = float(sum(r["M"] * r["P"] for r in reqs))
+
+    # plans made before any clock starts (server: one tiny request per plan key)
+    srv = ks.Server(slots=args.serve_slots, hbm_bytes=int(args.serve_hbm_gb * (1 << 30)))
+    first_of = {}
+    for k, r in enumerate(reqs):
+        first_of.setdefault((r["kernel"], r["d"], r["P"], r["data"]), k)
+    for j, (key, i) in enumerate(sorted(first_of.items())):
+        x, y, w, g = inputs(i)
+        s = torch.empty(1000, device=dev)
+        srv.submit(10**9 + j, key[0], key[1], key[2], x[:1000], y[:1000], w[:1000], s, params=params(i, "split_bf16"))
+    srv.drain()
+    srv.poll(100000)
+    plans = {key: ks.Plan(reqs[i]["d"], reqs[i]["P"], reqs[i]["kernel"], **params(i, "fp32"))
+             for key, i in first_of.items()}
+    torch.cuda.synchronize()
+
+    def summary(lat, makespan, extra):
+        out = {"p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+               "makespan_s": makespan, "value": work / makespan}
+        out.update(extra)
+        return out
+
+    def run_served(scale):
+        """Continuous batching with the split-BF16 projection; arrivals scaled by `scale`
+        (0 = every request queued at once)."""
+        lat, t_end_max, keep = [], 0.0, {}
+        t0 = time.monotonic()
+        i = pending = 0
+        while i < len(reqs) or pending:
+            now = time.monotonic() - t0
+            while i < len(reqs) and reqs[i]["arrival"] * scale <= now:
+                x, y, w, g = inputs(i)
+                s, gr = outputs(i)
+                keep[i] = (s, gr)
+                srv.submit(i, reqs[i]["kernel"], reqs[i]["d"], reqs[i]["P"], x, y, w, s,
+                           params=params(i, "split_bf16"), grad_s=g if reqs[i]["grad"] else None, grads=gr)
+                i += 1
+                pending += 1
+            for c in srv.poll(4096):
+                if c["status"] != 0:
+                    raise RuntimeError(f"request {c['tag']} failed with status {c['status']}")
+                lat.append(c["t_end"] - (t0 + reqs[c["tag"]]["arrival"] * scale))
+                t_end_max = max(t_end_max, c["t_end"] - t0)
+                keep.pop(c["tag"], None)
+                pending -= 1
+            time.sleep(5e-5)
+        st = srv.stats()
+        return summary(lat, t_end_max - reqs[0]["arrival"] * scale,
+                       {"precision": "split_bf16", "slots": args.serve_slots,
+                        "arena_peak_gb": st["arena_peak"] / 2**30})
+
+    def run_baseline(scale):
+        """One request at a time in arrival order, FP32, one stream."""
+        stream = torch.cuda.current_stream(dev)
+        lat = []
+        t0 = time.monotonic()
+        t_end = 0.0
+        for i, r in enumerate(reqs):
+            now = time.monotonic() - t0
+            if r["arrival"] * scale > now:
+                time.sleep(r["arrival"] * scale - now)
+            plan = plans[(r["kernel"], r["d"], r["P"], r["data"])]
+            x, y, w, g = inputs(i)
+            s = torch.empty(r["M"], device=dev)
+            plan(x, y, w, out=s, stream=stream)
+            if r["grad"]:
+                plan.backward(x, y, w, g, stream=stream)
+            torch.cuda.synchronize()
+            plan._ws = plan._bws = None        # one workspace at a time, reused through torch's cache
+            t_end = time.monotonic() - t0
+            lat.append(t_end - r["arrival"] * scale)
+        return summary(lat, t_end - reqs[0]["arrival"] * scale, {"precision": "fp32", "slots": 1})
+
+    served = run_served(1.0)
+    log(f"[serve] served at {args.serve_rate:g} req/s: p50 {served['p50_ms']:.2f} ms p99 {served['p99_ms']:.2f} ms, "
+        f"{served['value']:.3e} {UNIT} over {served['makespan_s']:.2f} s")
+    base = run_baseline(1.0)
+    log(f"[serve] one at a time at {args.serve_rate:g} req/s: p50 {base['p50_ms']:.2f} ms "
+        f"p99 {base['p99_ms']:.2f} ms, {base['value']:.3e} {UNIT} over {base['makespan_s']:.2f} s")
+    served_sat = run_served(0.0)
+    log(f"[serve] served, all queued at once: {served_sat['value']:.3e} {UNIT} over {served_sat['makespan_s']:.2f} s")
+    base_sat = run_baseline(0.0)
+    log(f"[serve] one at a time, all queued at once: {base_sat['value']:.3e} {UNIT} "
+        f"over {base_sat['makespan_s']:.2f} s")
+    srv.close()
+    result = {
+        "metric": METRIC, "value": served["value"], "unit": UNIT, "n_gpus": 1, "steps": len(reqs),
+        "warmup": len(first_of),
+        "ms_per_step": 1e3 * served["makespan_s"] / len(reqs), "p50_ms": served["p50_ms"], "p99_ms": served["p99_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+split_bf16",
+        "data": "synthetic",
+        "config": {"workload": "serve", "requests": len(reqs), "rate_per_s": args.serve_rate, "seed": 4,
+                   "N_M": "log-uniform [1e3, 5e5]", "d": list(SERVE_D), "P": [64, 256],
+                   "kernels": ["gaussian", "laplacian", "negdist"], "grad_fraction": 0.3},
+        "served": served, "one_at_a_time_fp32": base,
+        "p50_speedup": base["p50_ms"] / served["p50_ms"], "p99_speedup": base["p99_ms"] / served["p99_ms"],
+        "saturated": {"served": served_sat, "one_at_a_time_fp32": base_sat,
+                      "throughput_speedup": served_sat["value"] / base_sat["value"]},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="negdist", choices=sorted(wlm.WORKLOADS))
+    ap.add_argument("--workload", default="negdist", choices=sorted(wlm.WORKLOADS) + ["serve"])
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-hbm-gb", type=float, default=64.0)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in the CPU leg")
     ap.add_argument("--exact-targets", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -209,6 +377,10 @@ def main():
 
     import torch
     import paper_2401_08260_amd as ks
+
+    if args.workload == "serve":
+        bench_serve(args)
+        return
 
     if args.calibrate_copy:
         nbytes = 1 << 30

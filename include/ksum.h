@@ -234,6 +234,63 @@ ksum_status ksum_backward(ksum_plan *plan, const float *x, int64_t N, const floa
                           const float *grad_s, float *grad_x, float *grad_y, float *grad_w, void *ws,
                           size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Request server (continuous batching on one GPU).  A request is one forward sum
+ * (ksum_execute) and, when grad_s is not NULL, its backward (ksum_backward), with
+ * the plan given by (d, P, kernel, params).  ksum_server_submit queues it; a worker
+ * thread of the server starts queued requests in arrival order as soon as one of
+ * `slots` HIP streams is free and the request's workspace fits the server's HBM
+ * arena of `hbm_bytes` (admission by footprint; a request that does not fit lets
+ * later ones pass at most 16 times).  Requests run concurrently on their streams;
+ * plans are created once per distinct key and kept with their device tables.  All
+ * kernels are deterministic, so a result is bitwise the same alone and in the mix.
+ * Device pointers in a request are the caller's and must stay valid until the
+ * request's completion has been returned by ksum_server_poll.
+ * ------------------------------------------------------------------------- */
+typedef struct ksum_server ksum_server;
+
+typedef struct {
+  uint64_t tag;              /* caller's identifier, returned in the completion */
+  int32_t d, P;
+  ksum_kernel kernel;
+  ksum_params params;        /* params.directions and params.device are ignored */
+  const float *x;            /* device float[N][d] sources */
+  int64_t N;
+  const float *y;            /* device float[M][d] targets */
+  int64_t M;
+  const float *w;            /* device float[N] weights */
+  float *s;                  /* device float[M] output */
+  const float *grad_s;       /* device float[M] upstream gradient, or NULL for no backward */
+  float *grad_x, *grad_y, *grad_w;   /* backward outputs (each may be NULL) */
+} ksum_request;
+
+typedef struct {
+  uint64_t tag;
+  int32_t status;            /* ksum_status of the request */
+  double t_submit, t_start, t_end;   /* host steady-clock seconds: queued, started, seen complete */
+  size_t ws_bytes;           /* workspace the request held */
+} ksum_completion;
+
+typedef struct {
+  int64_t submitted, finished, queued, running, plans;
+  size_t arena_bytes, arena_used, arena_peak;
+} ksum_server_info;
+
+/* Create a server on `device` with `slots` streams (1..64) and an HBM arena of
+ * hbm_bytes (allocated once here).  EINVAL, ENOMEM, EDEVICE. */
+ksum_status ksum_server_create(int32_t device, int32_t slots, size_t hbm_bytes, ksum_server **out);
+/* Queue a request (copied; host call, returns at once).  EINVAL for missing
+ * pointers or bad sizes, the status of ksum_check_params for bad plan parameters. */
+ksum_status ksum_server_submit(ksum_server *server, const ksum_request *request);
+/* Move up to max_out finished requests into out (host array); *n_out = count. */
+ksum_status ksum_server_poll(ksum_server *server, ksum_completion *out, int32_t max_out, int32_t *n_out);
+/* Block until no request is queued or running. */
+ksum_status ksum_server_drain(ksum_server *server);
+/* Counters of the server (host). */
+ksum_status ksum_server_stats(ksum_server *server, ksum_server_info *info);
+/* Finish every queued request, then release the streams, plans and arena. */
+ksum_status ksum_server_destroy(ksum_server *server);
+
 /* Per-kernel timing (diagnostic).  While enabled, ksum_execute records HIP events
  * on its stream around every kernel it launches (a few microseconds of overhead
  * per kernel); ksum_stage_times synchronises with the last event and returns,

@@ -48,6 +48,24 @@ class ksum_probe(ctypes.Structure):
 
 
 _P = ctypes.c_void_p
+class ksum_request(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("d", ctypes.c_int32), ("P", ctypes.c_int32), ("kernel", ctypes.c_int),
+                ("params", ksum_params), ("x", ctypes.c_void_p), ("N", ctypes.c_int64), ("y", ctypes.c_void_p),
+                ("M", ctypes.c_int64), ("w", ctypes.c_void_p), ("s", ctypes.c_void_p), ("grad_s", ctypes.c_void_p),
+                ("grad_x", ctypes.c_void_p), ("grad_y", ctypes.c_void_p), ("grad_w", ctypes.c_void_p)]
+
+
+class ksum_completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_end", ctypes.c_double), ("ws_bytes", ctypes.c_size_t)]
+
+
+class ksum_server_info(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("finished", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("running", ctypes.c_int64), ("plans", ctypes.c_int64), ("arena_bytes", ctypes.c_size_t),
+                ("arena_used", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t)]
+
+
 _sigs = {
     "ksum_version": (ctypes.c_char_p, []),
     "ksum_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -73,6 +91,13 @@ _sigs = {
                                                     ctypes.POINTER(ctypes.c_size_t)]),
     "ksum_backward": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P, _P, _P, _P,
                                      ctypes.c_size_t, _P]),
+    "ksum_server_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER(_P)]),
+    "ksum_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(ksum_request)]),
+    "ksum_server_poll": (ctypes.c_int, [_P, ctypes.POINTER(ksum_completion), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "ksum_server_drain": (ctypes.c_int, [_P]),
+    "ksum_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(ksum_server_info)]),
+    "ksum_server_destroy": (ctypes.c_int, [_P]),
     "ksum_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ksum_stage_times": (ctypes.c_int, [_P, _P, _P]),
     "ksum_stage_count": (ctypes.c_int32, []),
@@ -355,3 +380,66 @@ def __getattr__(name):
         globals()["KernelSum"] = cls
         return cls
     raise AttributeError(name)
+
+
+class Server:
+    """Continuous-batching request server (ksum_server_* of the C ABI) bound to torch tensors.
+
+    srv = Server(slots=8, hbm_bytes=32 << 30)
+    srv.submit(tag, "gaussian", d, P, x, y, w, s, params=dict(sigma=..), grad_s=None, grads=(gx, gy, gw))
+    done = srv.poll()     # list of dicts {tag, status, t_submit, t_start, t_end, ws_bytes}
+    """
+
+    def __init__(self, slots: int = 8, hbm_bytes: int = 32 << 30, device: int = 0):
+        h = _P()
+        _check(_lib.ksum_server_create(device, slots, hbm_bytes, ctypes.byref(h)), "ksum_server_create")
+        self.handle = h.value
+        self._keep = {}          # tag -> tensors that must outlive the request
+
+    def submit(self, tag: int, kernel: str, d: int, P: int, x, y, w, s, params: Optional[dict] = None,
+               grad_s=None, grads=(None, None, None)) -> None:
+        kid = KERNELS[kernel]
+        r = ksum_request()
+        r.tag = tag
+        r.d, r.P, r.kernel = d, P, kid
+        r.params = make_params(kid, **(params or {}))
+        r.x, r.N, r.y, r.M = x.data_ptr(), x.shape[0], y.data_ptr(), y.shape[0]
+        r.w, r.s = w.data_ptr(), s.data_ptr()
+        gx, gy, gw = grads
+        r.grad_s = grad_s.data_ptr() if grad_s is not None else None
+        r.grad_x = gx.data_ptr() if gx is not None else None
+        r.grad_y = gy.data_ptr() if gy is not None else None
+        r.grad_w = gw.data_ptr() if gw is not None else None
+        self._keep[tag] = (x, y, w, s, grad_s, gx, gy, gw)
+        _check(_lib.ksum_server_submit(self.handle, ctypes.byref(r)), "ksum_server_submit")
+
+    def poll(self, max_out: int = 256):
+        buf = (ksum_completion * max_out)()
+        n = ctypes.c_int32()
+        _check(_lib.ksum_server_poll(self.handle, buf, max_out, ctypes.byref(n)), "ksum_server_poll")
+        out = []
+        for i in range(n.value):
+            c = buf[i]
+            self._keep.pop(c.tag, None)
+            out.append(dict(tag=c.tag, status=c.status, t_submit=c.t_submit, t_start=c.t_start, t_end=c.t_end,
+                            ws_bytes=c.ws_bytes))
+        return out
+
+    def drain(self) -> None:
+        _check(_lib.ksum_server_drain(self.handle), "ksum_server_drain")
+
+    def stats(self) -> dict:
+        info = ksum_server_info()
+        _check(_lib.ksum_server_stats(self.handle, ctypes.byref(info)), "ksum_server_stats")
+        return {k: getattr(info, k) for k, _ in ksum_server_info._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            _lib.ksum_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

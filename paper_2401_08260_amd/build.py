@@ -20,7 +20,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(HERE, "..", "include")]
 # gfx950 only; packed FP32 instructions are disabled for every HIP file
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["ksum_api.cpp", "host_tables.cpp", "k_project.hip", "k_setup.hip", "k_sort.hip",
+SOURCES = ["ksum_api.cpp", "host_tables.cpp", "server.cpp", "k_project.hip", "k_setup.hip", "k_sort.hip",
            "k_fourier.hip", "k_reduce.hip", "k_project_bf16.hip", "k_backproj.hip"]
 
 
@@ -41,7 +41,7 @@ def build_library(verbose: bool = True) -> str:
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs + ["-lpthread"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")

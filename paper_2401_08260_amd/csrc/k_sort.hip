@@ -288,7 +288,6 @@ struct RankState {
   uint32_t flag;
 };
 
-constexpr int kSortCapPad = kSortCap + kSortCap / 16;   // padded LDS arrays (pad16)
 constexpr int kNS = 2048;            // value-linear sub-buckets of a group sorted in LDS
 constexpr int kSubRunMax = 64;       // longest sub-bucket run sorted by insertion
 
