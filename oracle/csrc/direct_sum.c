@@ -3,7 +3,8 @@
  * Part of the FP64 CPU oracle (test infrastructure only).  Plain loops in the
  * order of the definition, FP64 arithmetic, one OpenMP thread per target block.
  * x: N*d, y: M*d, row-major; inputs may be FP32 or FP64 (converted exactly to FP64).
- * kernel: 1 Gaussian exp(-r^2/(2 sigma^2)), 2 Laplacian exp(-r/sigma), 3 negative distance -r.
+ * kernel: 1 Gaussian exp(-r^2/(2 sigma^2)), 2 Laplacian exp(-r/sigma), 3 negative distance -r,
+ *         4 Matern nu = 3/2 (1 + sqrt(3) r/sigma) exp(-sqrt(3) r/sigma).
  */
 #include <math.h>
 #include <stdint.h>
@@ -11,6 +12,10 @@
 static double basis(int kernel, double r2, double sigma) {
   if (kernel == 1) return exp(-r2 / (2.0 * sigma * sigma));
   if (kernel == 2) return exp(-sqrt(r2) / sigma);
+  if (kernel == 4) {
+    const double a = sqrt(3.0) * sqrt(r2) / sigma;
+    return (1.0 + a) * exp(-a);
+  }
   return -sqrt(r2);
 }
 

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "csrc", "direct_sum.c")
 _LIB = os.path.join(_HERE, "csrc", "liboracle_direct.so")
-_KERNEL_ID = {"gaussian": 1, "laplacian": 2, "negdist": 3}
+_KERNEL_ID = {"gaussian": 1, "laplacian": 2, "negdist": 3, "matern": 4}
 _lib = None
 
 

@@ -82,6 +82,9 @@ def slice_deriv(kernel: str, d: int, zx, zy, w, sigma: float, method: str, n_coe
         alpha = 1.0 / sigma
         ks2, cs = kn.laplace_smooth_coeffs(d, alpha / tau, K, laplace_L_factor * n_coeff)
         return ndft_deriv(xt, yt, w, ks2, cs, tau) + absdist_deriv_sum(zx, zy, w, alpha * kn.c_d(d))
+    if kernel == "matern":
+        ks2, cs = kn.matern_coeffs(d, sigma * tau, K, laplace_L_factor * n_coeff)
+        return ndft_deriv(xt, yt, w, ks2, cs, tau)
     raise ValueError(kernel)
 
 

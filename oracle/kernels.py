@@ -9,8 +9,11 @@ pairs used here are the rows of Table "tab:kernels":
              b_n = (-alpha)^n sqrt(pi) Gamma((n+d)/2) / (n! Gamma(d/2) Gamma((n+1)/2))
   neg. dist. F(r) = -r,                       f = -c_d t,
              c_d = sqrt(pi) Gamma((d+1)/2) / Gamma(d/2)   (Sec. 3.2)
+  Matern     nu = 3/2: F(r) = (1 + sqrt(3) r/beta) exp(-sqrt(3) r/beta), f from the
+             1F2 form of the appendix on the Matern and Laplacian kernels
 
-Parameters: `sigma` is the Gaussian bandwidth; the Laplacian uses alpha = 1/sigma.
+Parameters: `sigma` is the Gaussian bandwidth; the Laplacian uses alpha = 1/sigma;
+the Matern kernel uses beta = sigma.
 """
 from __future__ import annotations
 
@@ -19,7 +22,7 @@ import math
 import numpy as np
 from scipy.special import erfc
 
-KERNELS = ("gaussian", "laplacian", "negdist")
+KERNELS = ("gaussian", "laplacian", "negdist", "matern")
 
 
 def c_d(d: int) -> float:
@@ -36,6 +39,9 @@ def basis_F(kernel: str, r, sigma: float):
         return np.exp(-r / sigma)
     if kernel == "negdist":
         return -r
+    if kernel == "matern":
+        a = math.sqrt(3.0) * r / sigma
+        return (1.0 + a) * np.exp(-a)
     raise ValueError(kernel)
 
 
@@ -92,6 +98,39 @@ def _laplace_chains(d: int, t, alpha: float):
     return even, odd3, t1
 
 
+def _hyp1f2(a: float, b1: float, b2: float, z):
+    """1F2(a; b1, b2; z) by its power series, term ratio (a+n) z / ((b1+n) (b2+n) (n+1))."""
+    z = np.asarray(z, dtype=np.float64)
+    term = np.ones_like(z)
+    total = np.ones_like(z)
+    biggest = np.ones_like(z)
+    n = 0
+    while True:
+        term = term * (a + n) * z / ((b1 + n) * (b2 + n) * (n + 1.0))
+        n += 1
+        total = total + term
+        biggest = np.maximum(biggest, np.abs(term))
+        if n > 8 and np.all(np.abs(term) <= 1e-18 * biggest):
+            break
+        if n > 20000:
+            raise RuntimeError("1F2 series did not converge")
+    return total
+
+
+def matern32_f(d: int, t, beta: float):
+    """1-D counterpart of the Matern kernel with nu = 3/2 (appendix, 1F2 form):
+    f(t) = 1F2(d/2; 1/2, -1/2; z) + sqrt(3 pi) Gamma(d/2 + 3/2) / Gamma(d/2) (t/beta)^3
+           1F2(d/2 + 3/2; 2, 5/2; z),   z = 3 t^2 / (4 beta^2)
+    (the appendix's second term has the factor -Gamma(1 - nu) = 2 sqrt(pi) at nu = 3/2).
+    The two FP64 series cancel: the error grows with (t/beta)^2 d; it stays below 2e-8 f(0)
+    for (t/beta)^2 d <= 64 and reaches ~2e-7 f(0) at (t/beta)^2 d ~ 150, the edge of the
+    range that rescaled data with beta of the size of the median distance reach."""
+    x = np.abs(np.asarray(t, dtype=np.float64)) / beta
+    z = 0.75 * x * x
+    c3 = math.sqrt(3.0 * math.pi) * math.exp(math.lgamma(d / 2.0 + 1.5) - math.lgamma(d / 2.0))
+    return _hyp1f2(d / 2.0, 0.5, -0.5, z) + c3 * x ** 3 * _hyp1f2(d / 2.0 + 1.5, 2.0, 2.5, z)
+
+
 def counterpart_f(kernel: str, d: int, t, sigma: float):
     """The 1-D counterpart f(t), t >= 0 (fourth column of Table "tab:kernels")."""
     t = np.abs(np.asarray(t, dtype=np.float64))
@@ -102,6 +141,8 @@ def counterpart_f(kernel: str, d: int, t, sigma: float):
         return even + t1 + odd3
     if kernel == "negdist":
         return -c_d(d) * t
+    if kernel == "matern":
+        return matern32_f(d, t, sigma)
     raise ValueError(kernel)
 
 
@@ -138,6 +179,21 @@ def taper(u, center: float = 0.375, width: float = 1.0 / 37.0):
     return 0.5 * erfc((np.abs(np.asarray(u, dtype=np.float64)) - center) / width)
 
 
+def tapered_coeffs(phi, K: int, L: int):
+    """c_k = integral phi(u) W(u) exp(2 pi i k u) du, k = -K..K, on the torus [-1/2, 1/2) by the
+    trapezoidal rule on u_j = -1/2 + j/L (phi even, so c_k is real and even in k)."""
+    u = -0.5 + np.arange(L, dtype=np.float64) / L
+    vals = phi(u) * taper(u)
+    ks = np.arange(-K, K + 1)
+    # the trapezoidal sum (1/L) sum_j vals_j exp(2 pi i k u_j) with u_j = -1/2 + j/L is
+    # (-1)^k / L times the DFT of the samples (a library FFT evaluates it); phi is even,
+    # so the sum is real
+    F = np.fft.fft(vals)
+    kp = np.abs(ks)                                  # c_{-k} = c_k: take both from bin |k|
+    c = np.where(kp % 2 == 0, 1.0, -1.0) * F[kp % L].real / L
+    return ks, c
+
+
 def laplace_smooth_coeffs(d: int, alpha_t: float, K: int, L: int):
     """Fourier coefficients c_k, k = -K..K, of the tapered smooth part on the torus [-1/2, 1/2).
 
@@ -148,10 +204,11 @@ def laplace_smooth_coeffs(d: int, alpha_t: float, K: int, L: int):
     rule on u_j = -1/2 + j/L, j = 0..L-1 (exact up to aliasing for periodic phi).
     phi is even, so c_k is real and even in k.
     """
-    u = -0.5 + np.arange(L, dtype=np.float64) / L
-    vals = laplace_k1(d, alpha_t, u) * taper(u)
-    ks = np.arange(-K, K + 1, dtype=np.float64)
-    c = np.empty(ks.shape[0], dtype=np.float64)
-    for i, k in enumerate(ks):
-        c[i] = np.sum(vals * np.cos(2.0 * math.pi * k * u)) / L
-    return ks.astype(np.int64), c
+    return tapered_coeffs(lambda u: laplace_k1(d, alpha_t, u), K, L)
+
+
+def matern_coeffs(d: int, beta_t: float, K: int, L: int):
+    """Fourier coefficients of the tapered Matern counterpart f(|u|) in rescaled units
+    (beta_t = beta tau); f is continuously differentiable, so no part is split off (the
+    paper's Matern runs use the NFFT on f directly)."""
+    return tapered_coeffs(lambda u: matern32_f(d, u, beta_t), K, L)

@@ -18,7 +18,8 @@ Readings of passages that are garbled or silent (all listed in the design notes)
     c_{-n_coeff/2} := 0, i.e. k = -(n_coeff/2-1)..n_coeff/2-1.  (The NFFT is a fast
     approximation of the same NDFT, so the oracle evaluates the NDFT.)
   * Laplacian smooth part: coefficients from oracle.kernels.laplace_smooth_coeffs
-    with L = 16 n_coeff samples.
+    with L = 16 n_coeff samples; the Matern kernel (nu = 3/2) the same recipe on its
+    whole counterpart (oracle.kernels.matern_coeffs).
 """
 from __future__ import annotations
 
@@ -70,6 +71,9 @@ def slice_sum(kernel: str, d: int, zx, zy, w, sigma: float, method: str, n_coeff
         t1 = onedim.ndft_sum(xt, yt, w, ks2, cs)
         t2 = onedim.negdist_sum(zx, zy, w, alpha * kn.c_d(d))
         return t1 + t2
+    if kernel == "matern":
+        ks2, cs = kn.matern_coeffs(d, sigma * tau, K, laplace_L_factor * n_coeff)
+        return onedim.ndft_sum(xt, yt, w, ks2, cs)
     raise ValueError(kernel)
 
 

@@ -19,6 +19,8 @@ def _case(kernel, N=60, M=50, d=6, P=5, seed=0):
         kw = dict(sigma=1.0, method="sort", n_coeff=0, T=0.0)
     elif kernel == "gaussian":
         kw = dict(sigma=2.0, method="ndft", n_coeff=64, T=0.045)
+    elif kernel == "matern":
+        kw = dict(sigma=2.0, method="nfft", n_coeff=1024, T=0.125)
     else:
         kw = dict(sigma=2.0, method="nfft", n_coeff=256, T=0.125)
     return x, y, w, g, xi, kw
@@ -39,8 +41,10 @@ def test_absdist_deriv_hand_case_with_ties():
 
 # The Laplacian's smooth part k1 keeps the |u|^3 term of the series, so its Fourier
 # coefficients decay like k^-4 and the derivative of the truncated sum converges like
-# n_coeff^-3 (1.5e-5 relative at 256 coefficients, 5e-7 at 1024).
-@pytest.mark.parametrize("kernel,tol", [("negdist", 1e-9), ("gaussian", 1e-6), ("laplacian", 3e-5)])
+# n_coeff^-2.5 .. -3 (1.5e-5 relative at 256 coefficients, 5e-7 at 1024); the Matern
+# counterpart (nu = 3/2) has the same |u|^3 term (4e-6 at 1024 coefficients).
+@pytest.mark.parametrize("kernel,tol", [("negdist", 1e-9), ("gaussian", 1e-6), ("laplacian", 3e-5),
+                                        ("matern", 1e-5)])
 def test_slice_deriv_vs_brute_force(kernel, tol):
     rng = np.random.default_rng(4)
     d = 5
@@ -57,13 +61,13 @@ def test_slice_deriv_vs_brute_force(kernel, tol):
     assert np.linalg.norm(D - ref) <= tol * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("kernel", ["negdist", "gaussian", "laplacian"])
+@pytest.mark.parametrize("kernel", ["negdist", "gaussian", "laplacian", "matern"])
 def test_gradient_vs_central_differences(kernel):
     x, y, w, g, xi, kw = _case(kernel)
     gx, gy, gw = gradient.sliced_grad(kernel, x, y, w, g, xi, **kw)
     # |.| makes the negative distance and the Laplacian's sorted part piecewise smooth:
     # a step small enough not to cross a kink keeps central differences exact there
-    h = 1e-3 if kernel == "gaussian" else 1e-6
+    h = 1e-3 if kernel in ("gaussian", "matern") else 1e-6
     rng = np.random.default_rng(1)
     errs, refs = [], []
     for arr, grad in ((x, gx), (y, gy)):
@@ -79,7 +83,7 @@ def test_gradient_vs_central_differences(kernel):
             errs.append(fd - grad[i, j])
             refs.append(grad[i, j])
     errs, refs = np.array(errs), np.array(refs)
-    tol = 5e-5 if kernel == "laplacian" else 2e-6
+    tol = 5e-5 if kernel in ("laplacian", "matern") else 2e-6
     assert np.linalg.norm(errs) <= tol * np.linalg.norm(refs) + 1e-12
     # the sum is linear in w: central differences are exact up to rounding
     hw = 1e-2
@@ -93,7 +97,7 @@ def test_gradient_vs_central_differences(kernel):
         assert (lp - lm) / (2 * hw) == pytest.approx(gw[n], rel=1e-9, abs=1e-12)
 
 
-@pytest.mark.parametrize("kernel", ["negdist", "gaussian", "laplacian"])
+@pytest.mark.parametrize("kernel", ["negdist", "gaussian", "laplacian", "matern"])
 def test_gradient_translation_invariance(kernel):
     x, y, w, g, xi, kw = _case(kernel, seed=2)
     gx, gy, _ = gradient.sliced_grad(kernel, x, y, w, g, xi, **kw)

@@ -88,7 +88,7 @@ def test_laplace_k1_removes_linear_term():
 
 
 @pytest.mark.parametrize("kernel,d", [("gaussian", 3), ("gaussian", 10), ("laplacian", 4),
-                                      ("laplacian", 10), ("negdist", 7)])
+                                      ("laplacian", 10), ("negdist", 7), ("matern", 4), ("matern", 12)])
 def test_riemann_liouville_transform(kernel, d):
     """Prop. prop:sliced_kernels: F(s) = 2Gamma(d/2)/(sqrt(pi)Gamma((d-1)/2)) int_0^1 f(ts)(1-t^2)^((d-3)/2) dt."""
     sigma = 1.1
@@ -145,3 +145,35 @@ def test_laplace_smooth_coeffs_synthesis():
         assert np.array_equal(cs, cs[::-1])            # even in k
         synth = np.array([np.sum(cs * np.cos(2 * math.pi * ks * uu)) for uu in u])
         assert np.max(np.abs(synth - ref)) < tol * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("d", [1, 3])
+def test_matern_counterpart_closed_forms(d):
+    # d = 1: f = F; d = 3: f = F + t F' = (1 + a - a^2) exp(-a), a = sqrt(3) t / beta
+    t = np.linspace(0.0, 4.0, 41)
+    beta = 1.3
+    a = math.sqrt(3.0) * t / beta
+    ref = (1 + a) * np.exp(-a) if d == 1 else (1 + a - a * a) * np.exp(-a)
+    assert np.allclose(kn.counterpart_f("matern", d, t, beta), ref, rtol=1e-11, atol=1e-12)
+
+
+@pytest.mark.parametrize("d", [2, 7, 50, 3072])
+def test_matern_counterpart_vs_mpmath(d):
+    # the FP64 series cancel: for (t / beta)^2 d <= 64 the error stays below 2e-8 f(0)
+    beta = 0.8
+    tmax = 8.0 * beta / math.sqrt(d)
+    for t in (0.01 * tmax, 0.3 * tmax, tmax):
+        z = 0.75 * (t / beta) ** 2
+        ref = (mpmath.hyp1f2(mpmath.mpf(d) / 2, 0.5, -0.5, z)
+               + mpmath.sqrt(3 * mpmath.pi) * mpmath.gamma(mpmath.mpf(d) / 2 + 1.5) / mpmath.gamma(mpmath.mpf(d) / 2)
+               * (t / beta) ** 3 * mpmath.hyp1f2(mpmath.mpf(d) / 2 + 1.5, 2, 2.5, z))
+        assert abs(float(kn.counterpart_f("matern", d, t, beta)) - float(ref)) <= 2e-8
+
+
+def test_matern_coeffs_synthesis():
+    d, beta_t, K = 10, 0.3, 511
+    ks, c = kn.matern_coeffs(d, beta_t, K, 16 * 1024)
+    u = np.linspace(-0.25, 0.25, 101)
+    synth = (np.exp(2j * math.pi * np.outer(u, ks)) @ c).real
+    ref = kn.matern32_f(d, u, beta_t)
+    assert np.max(np.abs(synth - ref)) <= 1e-7 * np.max(np.abs(ref))

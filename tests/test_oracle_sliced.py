@@ -40,7 +40,7 @@ def test_median_heuristic_hand_case():
 
 # T = 0.1 for the Gaussian: data range ~4.5 sigma, so tau*sigma ~ 0.045 keeps |k| <= 32 enough
 @pytest.mark.parametrize("kernel,method,nc,T", [("gaussian", "ndft", 64, 0.1), ("negdist", "sort", 0, 0.0),
-                                                ("laplacian", "nfft", 256, 0.125)])
+                                                ("laplacian", "nfft", 256, 0.125), ("matern", "nfft", 1024, 0.125)])
 def test_d1_slicing_is_exact(kernel, method, nc, T):
     """d = 1: every direction is +-1 and f = F, so the sliced sum equals the exact sum for any P."""
     rng = np.random.default_rng(3)
@@ -52,7 +52,8 @@ def test_d1_slicing_is_exact(kernel, method, nc, T):
     s = sliced.sliced_sum(kernel, x, y, w, xi, sigma, method, nc, T)
     ref = direct.direct_sum(kernel, x, y, w, sigma)
     # Laplacian: the smooth part k1 has a |u|^3 kink, so 256 coefficients leave ~1e-7
-    tol = {"negdist": 1e-12, "gaussian": 1e-9, "laplacian": 3e-7}[kernel]
+    # Matern: f keeps a |u|^3 term too, 1024 coefficients leave ~1e-8
+    tol = {"negdist": 1e-12, "gaussian": 1e-9, "laplacian": 3e-7, "matern": 3e-8}[kernel]
     assert sliced.rel_l2(s, ref) < tol
 
 
@@ -111,6 +112,12 @@ def _brute_sliced(kernel, x, y, w, xi, sigma):
                     f = mpmath.hyp1f1(mpmath.mpf(d) / 2, 0.5, -t * t / (2 * sigma * sigma))
                 elif kernel == "negdist":
                     f = -kn.c_d(d) * t
+                elif kernel == "matern":
+                    z = 0.75 * (t / sigma) ** 2
+                    f = (mpmath.hyp1f2(mpmath.mpf(d) / 2, 0.5, -0.5, z)
+                         + mpmath.sqrt(3 * mpmath.pi) * mpmath.gamma(mpmath.mpf(d) / 2 + 1.5)
+                         / mpmath.gamma(mpmath.mpf(d) / 2) * (t / sigma) ** 3
+                         * mpmath.hyp1f2(mpmath.mpf(d) / 2 + 1.5, 2, 2.5, z))
                 else:
                     a = 1.0 / sigma
                     q = (a * t) ** 2 / 4
@@ -123,7 +130,7 @@ def _brute_sliced(kernel, x, y, w, xi, sigma):
 
 
 @pytest.mark.parametrize("kernel,method,nc,T", [("gaussian", "ndft", 64, 0.045), ("negdist", "sort", 0, 0.0),
-                                                ("laplacian", "nfft", 256, 0.125)])
+                                                ("laplacian", "nfft", 256, 0.125), ("matern", "nfft", 1024, 0.125)])
 def test_pipeline_vs_brute_force_tiny(kernel, method, nc, T):
     rng = np.random.default_rng(6)
     d = 5
@@ -134,7 +141,7 @@ def test_pipeline_vs_brute_force_tiny(kernel, method, nc, T):
     sigma = 0.9
     s = sliced.sliced_sum(kernel, x, y, w, xi, sigma, method, nc, T)
     ref = _brute_sliced(kernel, x, y, w, xi, sigma)
-    tol = {"negdist": 1e-13, "gaussian": 1e-8, "laplacian": 1e-7}[kernel]
+    tol = {"negdist": 1e-13, "gaussian": 1e-8, "laplacian": 1e-7, "matern": 1e-8}[kernel]
     assert sliced.rel_l2(s, ref) < tol
 
 
