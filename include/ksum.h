@@ -45,11 +45,15 @@ typedef struct ksum_plan ksum_plan;
 
 /* Kernels (Table "tab:kernels").  sigma is the Gaussian bandwidth,
  * K = exp(-||x-y||^2 / (2 sigma^2)); the Laplacian is K = exp(-alpha ||x-y||)
- * with alpha = 1/sigma; the negative distance kernel is K = -||x-y||. */
+ * with alpha = 1/sigma; the negative distance kernel is K = -||x-y||; the Matern
+ * kernel with nu = 3/2 is K = (1 + sqrt(3) r/beta) exp(-sqrt(3) r/beta), r = ||x-y||,
+ * beta = sigma (1-D counterpart: the 1F2 form of the appendix on the Matern and
+ * Laplacian kernels; Fourier summation by NFFT as in the paper's experiments). */
 typedef enum {
   KSUM_GAUSSIAN = 1,
   KSUM_LAPLACIAN = 2,
-  KSUM_NEGDIST = 3
+  KSUM_NEGDIST = 3,
+  KSUM_MATERN = 4
 } ksum_kernel;
 
 /* One-dimensional summation method.  AUTO picks NDFT for the Gaussian with at
@@ -89,12 +93,13 @@ typedef enum {
  *   seed        seed of the direction generator (see ksum_generate_directions)
  *   directions  optional host array P*d (FP64, row p = xi_p, unit norm) used instead
  *               of the generator; copied at plan creation; may be NULL
- *   n_coeff     Fourier coefficients: NDFT uses k = -n_coeff/2..n_coeff/2, NFFT the
+ *   n_coeff     Fourier coefficients (defaults: Gaussian 64, Laplacian 256, Matern 1024):
+ *               NDFT uses k = -n_coeff/2..n_coeff/2, NFFT the
  *               index set -n_coeff/2..n_coeff/2-1 with the coefficient at -n_coeff/2
  *               set to 0 (so the sum stays real); even, 2..4096
  *   coeff_eps   cutoff of eq. "Fourier_cutoff": coefficients with |c_k| <= eps are dropped
  *   T           rescaling threshold of Sec. 3.1, 0 < T < 0.25 (0 = method default:
- *               Gaussian NDFT 0.045, Gaussian NFFT 0.02, Laplacian 0.125)
+ *               Gaussian NDFT 0.045, Gaussian NFFT 0.02, Laplacian and Matern 0.125)
  *   oversample  NFFT grid oversampling (2 or 4); grid size n = oversample * n_coeff
  *   window_m    NFFT Kaiser-Bessel window half-width in grid cells (2..8)
  *   method      ksum_method

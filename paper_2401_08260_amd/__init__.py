@@ -24,13 +24,13 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 # enums (include/ksum.h)
-KSUM_GAUSSIAN, KSUM_LAPLACIAN, KSUM_NEGDIST = 1, 2, 3
+KSUM_GAUSSIAN, KSUM_LAPLACIAN, KSUM_NEGDIST, KSUM_MATERN = 1, 2, 3, 4
 KSUM_1D_AUTO, KSUM_1D_NDFT, KSUM_1D_NFFT, KSUM_1D_SORT = 0, 1, 2, 3
 KSUM_FP32, KSUM_SPLIT_BF16 = 0, 1
 PRECISIONS = {"fp32": KSUM_FP32, "split_bf16": KSUM_SPLIT_BF16}
 KSUM_OK, KSUM_EINVAL, KSUM_EUNSUPPORTED, KSUM_ENOMEM, KSUM_EWORKSPACE, KSUM_ENONFINITE, KSUM_EDEVICE = range(7)
 
-KERNELS = {"gaussian": KSUM_GAUSSIAN, "laplacian": KSUM_LAPLACIAN, "negdist": KSUM_NEGDIST}
+KERNELS = {"gaussian": KSUM_GAUSSIAN, "laplacian": KSUM_LAPLACIAN, "negdist": KSUM_NEGDIST, "matern": KSUM_MATERN}
 METHODS = {"auto": KSUM_1D_AUTO, "ndft": KSUM_1D_NDFT, "nfft": KSUM_1D_NFFT, "sort": KSUM_1D_SORT}
 
 

@@ -81,7 +81,8 @@ struct ksum_plan {
   double cd = 0;                 // c_d
   double sort_const = 0;         // constant of the sorted negative-distance part
   double gauss_logc = 0;         // log(d pi / sqrt(2)) - lgamma((d+2)/2)
-  int32_t lap_L = 0;             // samples of the Laplacian smooth-part recipe
+  double matern_c3 = 0;          // sqrt(3 pi) Gamma(d/2 + 3/2) / Gamma(d/2) (Matern, nu = 3/2)
+  int32_t lap_L = 0;             // samples of the tapered-coefficient recipe (Laplacian, Matern)
   std::vector<double> dirs;      // host directions, P x d
   ksum::WindowPoly poly{};
   // device tables

@@ -8,7 +8,8 @@
 //   * Laplacian smooth-part coefficients (Sec. 3.3): k1(u) = f(|u|/tau) + alpha c_d |u|/tau
 //     with its linear term removed, multiplied by the taper
 //     W(u) = erfc((|u| - 3/8) * 37) / 2 and integrated over the torus by the
-//     trapezoidal rule on L points;
+//     trapezoidal rule on L points; the Matern kernel (nu = 3/2) the same recipe on
+//     its whole counterpart f(|u|/tau);
 //   * the bucket map and fixed-point exponents of the sort path.
 // All coefficient arithmetic is FP64.
 #include "device_common.h"
@@ -24,7 +25,7 @@ struct SetupArgs {
   int32_t nfft;           // 1: fold the NFFT deconvolution into the table
   int32_t nb;             // buckets (sort path)
   int32_t lap_L;
-  double T, sigma, eps, gauss_logc, cd;
+  double T, sigma, eps, gauss_logc, cd, matern_c3;
   uint32_t *bounds;       // [nsl][2] min / max keys (written here from the partials)
   const uint32_t *part;   // [nparts][nsl][2] per-block partials of the projection, or null
   int32_t nparts;
@@ -37,23 +38,63 @@ struct SetupArgs {
   double *bounds_out;     // probe: [P][2] (already offset by p0) or null
 };
 
-// Even part (n = 0, 2, 4, ...) and odd part from n = 3 of the series of the
-// Laplacian counterpart f(t) = sum_n (-a)^n sqrt(pi) Gamma((n+d)/2) / (n! Gamma(d/2) Gamma((n+1)/2)),
-// a = alpha t (Table "tab:kernels").  Both chains follow
-// T_{n+2} = T_n a^2 (n+d) / ((n+1)^2 (n+2)), T_0 = 1, T_1 = -a c_d.
-__device__ double laplace_k1_series(double a, int d, double cd) {
+constexpr int kSeriesTab = 512;   // tabulated term ratios; longer series divide per term
+
+// Term ratios of the counterpart series, one table per chain (computed once per block):
+//  Laplacian (Table "tab:kernels"), a = alpha t: the even and odd chains of
+//    f(t) = sum_n (-a)^n sqrt(pi) Gamma((n+d)/2) / (n! Gamma(d/2) Gamma((n+1)/2)) follow
+//    T_{n+2} = T_n a^2 (n+d) / ((n+1)^2 (n+2)), T_0 = 1, T_1 = -a c_d;
+//  Matern nu = 3/2 (appendix), x = t / beta, z = 3 x^2 / 4:
+//    f = 1F2(d/2; 1/2, -1/2; z) + c3 x^3 1F2(d/2 + 3/2; 2, 5/2; z), a 1F2 term ratio being
+//    (a + n) z / ((b1 + n) (b2 + n) (n + 1)).
+struct SeriesTab {
+  double r0[kSeriesTab], r1[kSeriesTab];
+};
+
+__device__ __forceinline__ double lap_r0(int n, int d) {          // even chain, step n -> n + 2
+  return (double)(n + d) / ((double)(n + 1) * (double)(n + 1) * (double)(n + 2));
+}
+__device__ __forceinline__ double lap_r1(int n, int d) {          // odd chain, step n + 1 -> n + 3
+  return (double)(n + 1 + d) / ((double)(n + 2) * (double)(n + 2) * (double)(n + 3));
+}
+__device__ __forceinline__ double mat_r0(int n, int d) {
+  return (0.5 * d + n) / ((0.5 + n) * (n - 0.5) * (n + 1.0));
+}
+__device__ __forceinline__ double mat_r1(int n, int d) {
+  return (0.5 * d + 1.5 + n) / ((2.0 + n) * (2.5 + n) * (n + 1.0));
+}
+
+// Laplacian smooth part k1 at a = alpha t: the series with its linear term removed
+// (index i of the tables is the step n = 2 i).
+__device__ double laplace_k1_series(double a, int d, double cd, const SeriesTab &tb) {
   const double a2 = a * a;
   double te = 1.0, to = -a * cd;
   double even = 1.0, odd3 = 0.0, big = 1.0;
-  for (int n = 0; n < 20000; n += 2) {
-    te *= a2 * (double)(n + d) / ((double)(n + 1) * (double)(n + 1) * (double)(n + 2));
-    to *= a2 * (double)(n + 1 + d) / ((double)(n + 2) * (double)(n + 2) * (double)(n + 3));
+  for (int n = 0; n < 40000; n += 2) {
+    const int i = n >> 1;
+    te *= a2 * (i < kSeriesTab ? tb.r0[i] : lap_r0(n, d));
+    to *= a2 * (i < kSeriesTab ? tb.r1[i] : lap_r1(n, d));
     even += te;
     odd3 += to;
     big = fmax(big, fmax(fabs(te), fabs(to)));
     if (n > 8 && fabs(te) + fabs(to) <= 1e-18 * big) break;
   }
   return even + odd3;
+}
+
+// Matern (nu = 3/2) counterpart at x = t / beta.
+__device__ double matern32_series(double x, int d, double c3, const SeriesTab &tb) {
+  const double z = 0.75 * x * x;
+  double ta = 1.0, tb1 = 1.0, sa = 1.0, sb = 1.0, big = 1.0;
+  for (int n = 0; n < 40000; ++n) {
+    ta *= z * (n < kSeriesTab ? tb.r0[n] : mat_r0(n, d));
+    tb1 *= z * (n < kSeriesTab ? tb.r1[n] : mat_r1(n, d));
+    sa += ta;
+    sb += tb1;
+    big = fmax(big, fmax(fabs(ta), fabs(tb1)));
+    if (n > 8 && fabs(ta) + fabs(tb1) <= 1e-18 * big) break;
+  }
+  return sa + c3 * x * x * x * sb;
 }
 
 __global__ __launch_bounds__(256) void slice_setup_kernel(SetupArgs a) {
@@ -135,32 +176,73 @@ __global__ __launch_bounds__(256) void slice_setup_kernel(SetupArgs a) {
     }
     return;
   }
-  if (a.kernel == KSUM_LAPLACIAN) {
-    const double alpha_t = 1.0 / (a.sigma * sp.tau);   // alpha / tau
-    const int L = a.lap_L;
-    double *v = a.lapv + (int64_t)p * L;
-    for (int j = threadIdx.x; j < L; j += blockDim.x) {
-      const double u = -0.5 + (double)j / (double)L;
-      const double au = fabs(u);
-      const double taper = 0.5 * erfc((au - 0.375) * 37.0);
-      v[j] = laplace_k1_series(alpha_t * au, a.d, a.cd) * taper;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k <= a.K; k += blockDim.x) {
-      // c_k = (1/L) sum_j v_j cos(2 pi k u_j),  cos(2 pi k (-1/2 + j/L)) = (-1)^k cos(2 pi k j / L)
-      double acc = 0.0;
-      int idx = 0;
-      for (int j = 0; j < L; ++j) {
-        acc += v[j] * a.costab[idx];
-        idx += k;
-        if (idx >= L) idx -= L;
+  // Tapered-coefficient recipe (Laplacian smooth part, Matern): samples v_j of the
+  // function times the taper on u_j = -1/2 + j/L, then c_k = (1/L) sum_j v_j cos(2 pi k u_j).
+  __shared__ SeriesTab tab;
+  __shared__ double part[512];
+  const bool lap = (a.kernel == KSUM_LAPLACIAN);
+  for (int i = threadIdx.x; i < kSeriesTab; i += blockDim.x) {
+    tab.r0[i] = lap ? lap_r0(2 * i, a.d) : mat_r0(i, a.d);
+    tab.r1[i] = lap ? lap_r1(2 * i, a.d) : mat_r1(i, a.d);
+  }
+  __syncthreads();
+  const int L = a.lap_L;
+  double *v = a.lapv + (int64_t)p * L;
+  const double inv_scale = 1.0 / (a.sigma * sp.tau);   // alpha / tau, or 1 / (beta tau)
+  for (int j = threadIdx.x; j < L; j += blockDim.x) {
+    const double u = -0.5 + (double)j / (double)L;
+    const double au = fabs(u);
+    const double taper = 0.5 * erfc((au - 0.375) * 37.0);
+    const double f = lap ? laplace_k1_series(inv_scale * au, a.d, a.cd, tab)
+                         : matern32_series(inv_scale * au, a.d, a.matern_c3, tab);
+    v[j] = f * taper;
+  }
+  __syncthreads();
+  // DFT: c_k = (1/L) sum_j v_j cos(2 pi k u_j) = (-1)^k (1/L) sum_j v_j cos(2 pi k j / L), the
+  // cosine by rotation from the exact table value every 64 steps.  With few coefficients
+  // the j range of each k is split over S threads and the partial sums added in order.
+  const int K1 = a.K + 1;
+  const int qL = L / 4;                    // sin(x) = cos(x - pi/2)
+  auto dft_range = [&](int k, int j0, int j1) {
+    const int kst = k % L;
+    const double cr = a.costab[kst], sr = a.costab[(kst - qL + L) % L];
+    double acc = 0.0;
+    for (int jb = j0; jb < j1; jb += 64) {
+      const int idx = (int)(((int64_t)k * jb) % L);
+      double c = a.costab[idx], s = a.costab[(idx - qL + L) % L];
+      const int je = min(jb + 64, j1);
+      for (int j = jb; j < je; ++j) {
+        acc += v[j] * c;
+        const double cn = c * cr - s * sr;
+        s = s * cr + c * sr;
+        c = cn;
       }
-      double c = acc / (double)L;
-      if (k & 1) c = -c;
-      if (fabs(c) <= a.eps) c = 0.0;
-      if (a.nfft) c *= (double)a.deconv[k];
-      coef[k] = (float)c;
     }
+    return acc;
+  };
+  auto finish = [&](int k, double acc) {
+    double c = acc / (double)L;
+    if (k & 1) c = -c;
+    if (fabs(c) <= a.eps) c = 0.0;
+    if (a.nfft) c *= (double)a.deconv[k];
+    coef[k] = (float)c;
+  };
+  const int S = (K1 >= (int)blockDim.x) ? 1 : min(8, (int)blockDim.x / K1);   // K1 * S <= 512
+  if (S == 1) {
+    for (int k = threadIdx.x; k < K1; k += blockDim.x) finish(k, dft_range(k, 0, L));
+    return;
+  }
+  const int span = (L / S + 63) / 64 * 64;
+  for (int it = threadIdx.x; it < K1 * S; it += blockDim.x) {
+    const int k = it % K1, sidx = it / K1;
+    const int j0 = min(L, sidx * span), j1 = min(L, j0 + span);
+    part[it] = dft_range(k, j0, j1);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K1; k += blockDim.x) {
+    double acc = 0.0;
+    for (int sidx = 0; sidx < S; ++sidx) acc += part[sidx * K1 + k];
+    finish(k, acc);
   }
 }
 
@@ -180,6 +262,7 @@ hipError_t launch_slice_setup(const ExecArgs &a) {
   s.eps = pl.params.coeff_eps;
   s.gauss_logc = pl.gauss_logc;
   s.cd = pl.cd;
+  s.matern_c3 = pl.matern_c3;
   s.bounds = wsp<uint32_t>(a, lay.off_bounds);
   s.part = wsp<uint32_t>(a, lay.off_bounds_part);
   s.nparts = projection_blocks(*a.plan, lay.L, a.nsl);

@@ -62,7 +62,7 @@ static int resolve_method(ksum_kernel kernel, const ksum_params &p) {
 static double resolve_T(ksum_kernel kernel, int method, double T) {
   if (T > 0.0) return T;
   if (kernel == KSUM_GAUSSIAN) return method == KSUM_1D_NDFT ? 0.045 : 0.02;
-  if (kernel == KSUM_LAPLACIAN) return 0.125;
+  if (kernel == KSUM_LAPLACIAN || kernel == KSUM_MATERN) return 0.125;
   return 0.0;
 }
 
@@ -78,7 +78,7 @@ static void nfft_window(int n, double T, int m, int *lo, int *cells) {
 static ksum_status validate(int32_t d, int32_t P, ksum_kernel kernel, const ksum_params &p) {
   if (d < 1 || d > (1 << 20)) return fail(KSUM_EINVAL, "d must be in [1, 2^20]");
   if (P < 1 || P > (1 << 24)) return fail(KSUM_EINVAL, "P must be in [1, 2^24]");
-  if (kernel != KSUM_GAUSSIAN && kernel != KSUM_LAPLACIAN && kernel != KSUM_NEGDIST)
+  if (kernel != KSUM_GAUSSIAN && kernel != KSUM_LAPLACIAN && kernel != KSUM_NEGDIST && kernel != KSUM_MATERN)
     return fail(KSUM_EINVAL, "unknown kernel");
   if (p.method < KSUM_1D_AUTO || p.method > KSUM_1D_SORT) return fail(KSUM_EINVAL, "unknown method");
   if (p.precision != KSUM_FP32 && p.precision != KSUM_SPLIT_BF16)
@@ -152,7 +152,7 @@ Layout make_layout(const ksum_plan &pl, int64_t N, int64_t M) {
       y.off_fpart = take((size_t)B * y.nfft_chunks * y.win_cells * sizeof(float));
       y.off_grid = take((size_t)B * y.win_cells * sizeof(float));
     }
-    if (pl.kernel == KSUM_LAPLACIAN) y.off_lapv = take((size_t)B * pl.lap_L * sizeof(double));
+    if (pl.lap_L > 0) y.off_lapv = take((size_t)B * pl.lap_L * sizeof(double));
   }
   if (pl.use_sort) {
     const int64_t L = y.L;
@@ -177,7 +177,7 @@ static void fill_defaults(ksum_kernel kernel, ksum_params *p) {
   p->sigma = 1.0;
   p->seed = 0;
   p->directions = nullptr;
-  p->n_coeff = (kernel == KSUM_LAPLACIAN) ? 256 : 64;
+  p->n_coeff = (kernel == KSUM_LAPLACIAN) ? 256 : (kernel == KSUM_MATERN) ? 1024 : 64;
   p->coeff_eps = 0.0;
   p->T = 0.0;
   p->oversample = 2;
@@ -233,7 +233,7 @@ const char *ksum_last_error(void) { return g_last_error.c_str(); }
 
 ksum_status ksum_params_default(ksum_kernel kernel, ksum_params *out) {
   if (!out) return fail(KSUM_EINVAL, "out is NULL");
-  if (kernel != KSUM_GAUSSIAN && kernel != KSUM_LAPLACIAN && kernel != KSUM_NEGDIST)
+  if (kernel != KSUM_GAUSSIAN && kernel != KSUM_LAPLACIAN && kernel != KSUM_NEGDIST && kernel != KSUM_MATERN)
     return fail(KSUM_EINVAL, "unknown kernel");
   fill_defaults(kernel, out);
   return KSUM_OK;
@@ -274,10 +274,11 @@ static ksum_status plan_host_setup(int32_t d, int32_t P, ksum_kernel kernel, con
   pl->cd = std::sqrt(M_PI) * std::exp(std::lgamma((d + 1) / 2.0) - std::lgamma(d / 2.0));
   pl->sort_const = (kernel == KSUM_LAPLACIAN) ? pl->cd / p.sigma : pl->cd;
   pl->gauss_logc = std::log((double)d * M_PI / std::sqrt(2.0)) - std::lgamma((d + 2) / 2.0);
+  pl->matern_c3 = std::sqrt(3.0 * M_PI) * std::exp(std::lgamma(d / 2.0 + 1.5) - std::lgamma(d / 2.0));
   if (pl->use_fourier) {
     pl->K = (pl->method == KSUM_1D_NDFT) ? p.n_coeff / 2 : p.n_coeff / 2 - 1;
     if (pl->method == KSUM_1D_NFFT) pl->n_grid = p.oversample * p.n_coeff;
-    if (kernel == KSUM_LAPLACIAN) pl->lap_L = 16 * p.n_coeff;
+    if (kernel == KSUM_LAPLACIAN || kernel == KSUM_MATERN) pl->lap_L = 16 * p.n_coeff;
   }
   pl->dirs.resize((size_t)P * d);
   if (params && params->directions) {
@@ -387,7 +388,7 @@ ksum_status ksum_plan_create(int32_t d, int32_t P, ksum_kernel kernel, const ksu
         hipMemcpy(pl->d_twiddle, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
       return dev_fail(KSUM_EDEVICE, "hipMemcpy");
   }
-  if (pl->kernel == KSUM_LAPLACIAN) {
+  if (pl->lap_L > 0) {
     std::vector<double> ct(pl->lap_L);
     for (int j = 0; j < pl->lap_L; ++j) ct[j] = std::cos(2.0 * M_PI * (double)j / (double)pl->lap_L);
     if (hipMalloc(&pl->d_costab, ct.size() * sizeof(double)) != hipSuccess) return dev_fail(KSUM_ENOMEM, "hipMalloc");

@@ -165,3 +165,16 @@ def test_backward_split_bf16():
     # grad_w is compared with the FP64-projection oracle: the split-BF16 projection's
     # error enters it as in the forward (the mixed-precision gate of the forward tests)
     check("negdist", x, y, w, g, P, seed=3, tol=1e-4, precision="split_bf16")
+
+
+def test_backward_matern_reduced():
+    rng = np.random.default_rng(31)
+    N, M, d, P = 6000, 5000, 20, 3
+    x = rng.standard_normal((N, d)).astype(np.float32)
+    y = rng.standard_normal((M, d)).astype(np.float32)
+    w = rng.random(N).astype(np.float32)
+    g = rng.standard_normal(M).astype(np.float32)
+    beta = wlm.median_heuristic(x, y)
+    note("backward matern")
+    kw = dict(sigma=beta, method="nfft", n_coeff=1024, T=0.125)
+    check("matern", x, y, w, g, P, seed=2, ref_kw=kw, **kw)

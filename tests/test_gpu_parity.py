@@ -212,3 +212,17 @@ def test_negdist_workload_full_size():
     err = sliced.rel_l2(r["s"], ref)
     note(f"  rel err {err:.3e}")
     assert err <= TOL
+
+
+def test_matern_reduced():
+    """Matern nu = 3/2 with the paper's NFFT setting (1024 coefficients), mixture data."""
+    wl = wlm.scaled(wlm.WORKLOADS["gauss_nfft"], N=20000, M=15000, P=4)
+    x, y, w = wlm.generate(wl)
+    beta = wlm.median_heuristic(x, y)
+    note("matern reduced")
+    r = run_gpu("matern", x, y, w, wl.P, seed=6, sigma=beta, n_coeff=1024, T=0.125, probe=True)
+    ref, ts = oracle_s("matern", x, y, w, r["xi"], beta, "nfft", 1024, 0.125, slices=True)
+    err = sliced.rel_l2(r["s"], ref)
+    note(f"  rel err {err:.3e}")
+    assert err <= TOL
+    assert sliced.rel_l2(r["t"].astype(np.float64), ts) <= TOL
