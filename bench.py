@@ -151,11 +151,17 @@ def cpu_baseline(wl, x, y, w, sigma, xi, s_gpu, t_gpu, budget_s, exact_targets, 
     except Exception:  # pragma: no cover
         blas_threads = os.cpu_count() or 1
     method = "sort" if wl.kernel == "negdist" else wl.method
-    # size the sample: one slice first, then as many as the budget allows
-    t0 = time.perf_counter()
-    _, ts1 = sliced.sliced_sum(wl.kernel, x, y, w, xi[:1], sigma, method, wl.n_coeff, wl.T, return_slices=True)
-    one = time.perf_counter() - t0
-    Q = int(max(1, min(wl.P, budget_s / max(one, 1e-3))))
+    # size the sample from the marginal cost of a slice (the first call also pays for
+    # converting the points), then take as many slices as the budget allows
+    def run(q):
+        t0 = time.perf_counter()
+        sliced.sliced_sum(wl.kernel, x, y, w, xi[:q], sigma, method, wl.n_coeff, wl.T, return_slices=True)
+        return time.perf_counter() - t0
+    q1 = min(wl.P, 4)
+    t1 = run(1)
+    tq = run(q1) if q1 > 1 else t1
+    per = max((tq - t1) / max(q1 - 1, 1), tq / q1 * 0.25, 1e-4)
+    Q = int(max(1, min(wl.P, (budget_s - t1) / per)))
     t0 = time.perf_counter()
     _, ts = sliced.sliced_sum(wl.kernel, x, y, w, xi[:Q], sigma, method, wl.n_coeff, wl.T, return_slices=True)
     dt = time.perf_counter() - t0

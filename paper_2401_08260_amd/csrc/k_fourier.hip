@@ -13,9 +13,9 @@
 // c_k / (n phi^(k))^2 (deconvolution of both window passes), transformed back,
 // and interpolated at the targets with the same window.  Points only occupy
 // [-T, T], so spreading and interpolation touch a window of W cells around 0;
-// each lane accumulates into its own copy of that window in LDS ([cell][lane]
-// layout: conflict-free, deterministic), then lanes and chunks are reduced in a
-// fixed order.
+// the spread accumulates into copies of that window in LDS, one per lane or per
+// few lanes ([cell][copy] layout: conflict-free, deterministic), then copies and
+// chunks are reduced in a fixed order.
 #include <algorithm>
 
 #include "device_common.h"
@@ -42,7 +42,7 @@ struct FourierArgs {
   float *t;                // [nsl][M]
   // NFFT
   int32_t n, W, lo;        // grid size, window cells, first window cell (may be < 0)
-  int32_t lanes;           // lanes per spread block
+  int32_t share;           // lanes per window copy in the spread (1..64)
   int32_t i0min, i0max;    // clamp of the base cell
   const float2 *twiddle;   // [n]
   WindowPoly poly;
@@ -190,22 +190,30 @@ __device__ __forceinline__ void window_taps(const WindowPoly &wp, float x, float
   }
 }
 
-template <int MW, int DEG, int LANES>
-__global__ __launch_bounds__(LANES) void nfft_spread_kernel(FourierArgs a) {
-  extern __shared__ float acc[];   // [W][LANES]
+// Spreading of one chunk of 256 x kNfftPPL sources of a slice.  The W-cell window
+// is kept in LDS as 256/SH copies ([cell][copy]); SH lanes of a wave share a copy and
+// update it one after the other (SH phases in lane order), so every copy sees its
+// updates in a fixed order and the result is deterministic.  SH grows with the
+// window so that wide windows (the Laplacian's and Matern's T = 1/8) still leave
+// room for several blocks per CU.
+template <int MW, int DEG, int SH>
+__global__ __launch_bounds__(256) void nfft_spread_kernel(FourierArgs a) {
+  extern __shared__ float acc[];   // [W][NC]
+  constexpr int CW = 64 / SH;      // copies per wave
+  constexpr int NC = 256 / SH;     // copies per block
   const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * a.chunks);
   if (work < 0) return;
   const int p = (int)(work / a.chunks), c = (int)(work % a.chunks);
-  const int lanes = LANES;
-  const int t = threadIdx.x;
-  for (int i = t; i < a.W * lanes; i += lanes) acc[i] = 0.f;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int copy = wid * CW + lane % CW, phase = lane / CW;
+  for (int i = t; i < a.W * NC; i += 256) acc[i] = 0.f;
   __syncthreads();
   const SliceParams sp = a.params[p];
   const float *Zx = a.Z + (int64_t)p * a.L + a.M;
-  const int64_t chunk = (int64_t)lanes * kNfftPPL;
+  const int64_t chunk = (int64_t)256 * kNfftPPL;
   const int64_t n0 = (int64_t)c * chunk, n1 = min(a.N, n0 + chunk);
   const float fn = (float)a.n;
-  for (int64_t i = n0 + t; i < n1; i += lanes) {
+  for (int64_t i = n0 + t; i < n1; i += 256) {
     const float xt = (Zx[i] - sp.fcmin) * sp.ftau + sp.shift;
     const float u = xt * fn;
     int i0 = (int)floorf(u);
@@ -214,21 +222,25 @@ __global__ __launch_bounds__(LANES) void nfft_spread_kernel(FourierArgs a) {
     float tap[2 * MW];
     window_taps<MW, DEG>(a.poly, fr - 0.5f, tap);
     const float wv = a.w[i];
-    // the 2 MW cells of this lane's window copy are distinct: read them all, then write
-    float *base = acc + (i0 - MW + 1 - a.lo) * lanes + t;
-    float v[2 * MW];
+    // the 2 MW cells of this lane's copy are distinct: read them all, then write
+    float *base = acc + (i0 - MW + 1 - a.lo) * NC + copy;
+#pragma unroll 1
+    for (int ph = 0; ph < SH; ++ph) {
+      if (phase == ph) {
+        float v[2 * MW];
 #pragma unroll
-    for (int j = 0; j < 2 * MW; ++j) v[j] = base[j * lanes];
+        for (int j = 0; j < 2 * MW; ++j) v[j] = base[j * NC];
 #pragma unroll
-    for (int j = 0; j < 2 * MW; ++j) base[j * lanes] = fmaf(wv, tap[j], v[j]);
+        for (int j = 0; j < 2 * MW; ++j) base[j * NC] = fmaf(wv, tap[j], v[j]);
+      }
+    }
   }
   __syncthreads();
-  // reduce the lanes of every cell in a fixed order: one wave per cell
-  const int lane = t & 63, wid = t >> 6, nw = lanes >> 6;
+  // reduce the copies of every cell in a fixed order: one wave per cell
   float *out = a.gpart + ((int64_t)p * a.chunks + c) * a.W;
-  for (int cell = wid; cell < a.W; cell += nw) {
+  for (int cell = wid; cell < a.W; cell += 4) {
     float s = 0.f;
-    for (int l = lane; l < lanes; l += 64) s += acc[cell * lanes + l];
+    for (int l = lane; l < NC; l += 64) s += acc[cell * NC + l];
     s = wave_sum(s);
     if (lane == 0) out[cell] = s;
   }
@@ -383,38 +395,43 @@ __global__ __launch_bounds__(256) void nfft_interp_accum_kernel(FourierArgs a, A
   }
 }
 
+template <int MW, int DEG, int SH>
+static void launch_spread_sh(const FourierArgs &f, const ExecArgs &a, unsigned gs) {
+  const size_t lds = (size_t)f.W * (256 / SH) * sizeof(float);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void *)nfft_spread_kernel<MW, DEG, SH>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  nfft_spread_kernel<MW, DEG, SH><<<gs, 256, lds, a.stream>>>(f);
+}
+
 template <int MW, int DEG>
 static void launch_nfft_m(const FourierArgs &f, const ExecArgs &a) {
   const unsigned gs = (unsigned)xcd_grid((int64_t)a.nsl * f.chunks);
-  const size_t spread_lds = (size_t)f.W * f.lanes * sizeof(float);
   const size_t grid_lds = 2 * (size_t)f.n * sizeof(float2);
-  if (spread_lds > 65536) {
-    (void)hipFuncSetAttribute((const void *)nfft_spread_kernel<MW, DEG, 256>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)spread_lds);
-    (void)hipFuncSetAttribute((const void *)nfft_spread_kernel<MW, DEG, 128>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)spread_lds);
-    (void)hipFuncSetAttribute((const void *)nfft_spread_kernel<MW, DEG, 64>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)spread_lds);
-  }
   if (grid_lds > 65536)
     (void)hipFuncSetAttribute((const void *)nfft_grid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)grid_lds);
   mark(a, ST_NFFT_SPREAD);
-  if (f.lanes == 256)
-    nfft_spread_kernel<MW, DEG, 256><<<gs, 256, spread_lds, a.stream>>>(f);
-  else if (f.lanes == 128)
-    nfft_spread_kernel<MW, DEG, 128><<<gs, 128, spread_lds, a.stream>>>(f);
-  else
-    nfft_spread_kernel<MW, DEG, 64><<<gs, 64, spread_lds, a.stream>>>(f);
+  switch (f.share) {
+    case 1: launch_spread_sh<MW, DEG, 1>(f, a, gs); break;
+    case 2: launch_spread_sh<MW, DEG, 2>(f, a, gs); break;
+    case 4: launch_spread_sh<MW, DEG, 4>(f, a, gs); break;
+    case 8: launch_spread_sh<MW, DEG, 8>(f, a, gs); break;
+    case 16: launch_spread_sh<MW, DEG, 16>(f, a, gs); break;
+    case 32: launch_spread_sh<MW, DEG, 32>(f, a, gs); break;
+    default: launch_spread_sh<MW, DEG, 64>(f, a, gs); break;
+  }
   mark(a, ST_NFFT_GRID);
   nfft_grid_kernel<<<a.nsl, 256, grid_lds, a.stream>>>(f);
 }
 
-int nfft_lanes_for(int W) {
-  // lanes per spread block: as many as fit 64 KB of per-lane windows (>= 64)
-  int lanes = 256;
-  while (lanes > 64 && (size_t)W * lanes * sizeof(float) > 64 * 1024) lanes >>= 1;
-  return lanes;
+// Lanes per window copy of the spread: the smallest power of two that keeps a
+// 256-thread block's copies within 40 KB (several blocks per CU); 0 if even 64
+// lanes per copy (4 copies) do not fit 64 KB.
+int nfft_share_for(int W) {
+  for (int sh = 1; sh <= 64; sh <<= 1)
+    if ((size_t)W * (256 / sh) * sizeof(float) <= 40 * 1024) return sh;
+  return ((size_t)W * 4 * sizeof(float) <= 64 * 1024) ? 64 : 0;
 }
 
 static FourierArgs nfft_args(const ExecArgs &a) {
@@ -437,7 +454,7 @@ static FourierArgs nfft_args(const ExecArgs &a) {
   f.n = pl.n_grid;
   f.W = lay.win_cells;
   f.lo = lay.win_lo;
-  f.lanes = nfft_lanes_for(lay.win_cells);
+  f.share = nfft_share_for(lay.win_cells);
   const int m = pl.params.window_m;
   f.i0min = lay.win_lo + m - 1;
   f.i0max = lay.win_lo + lay.win_cells - 1 - m;

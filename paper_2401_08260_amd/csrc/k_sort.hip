@@ -842,6 +842,7 @@ __device__ __forceinline__ int sub_bucket(uint32_t key, float zlo, float inv) {
 // canonical (key, index) order (so the rounding is the same on every run), on
 // top of the exact fixed-point prefix of the group's first bucket.  W holds the
 // weights of the sources (0 for targets).  Thread t owns entries [8t, 8t+8).
+template <bool DERIV>
 __device__ __forceinline__ void scan_emit_fast(const SortArgs &a, int p, const SliceParams &sp, int eA,
                                                const FastShared &f, int n, int64_t out_pos, long long preA,
                                                long long preS, long long totA, long long totS, double *smd) {
@@ -862,7 +863,7 @@ __device__ __forceinline__ void scan_emit_fast(const SortArgs &a, int p, const S
       kk[q] = f.K[e];
       ii[q] = f.I[e];
       ww[q] = ((int64_t)ii[q] >= a.M) ? f.W[e] : 0.f;
-      if (a.deriv && (int64_t)ii[q] < a.M) eqw[q] = f.W[e];
+      if (DERIV && (int64_t)ii[q] < a.M) eqw[q] = f.W[e];
       lA += (double)ww[q];
       lS += (double)ww[q] * ((double)key_float(kk[q]) - sp.cmid);
     }
@@ -878,7 +879,7 @@ __device__ __forceinline__ void scan_emit_fast(const SortArgs &a, int p, const S
     if (j < n) {
       const double zb = (double)key_float(kk[q]) - sp.cmid;
       if ((int64_t)ii[q] < a.M) {
-        if (a.deriv)
+        if (DERIV)
           tp[ii[q]] = (float)(-a.cneg * (2.0 * exA + (double)eqw[q] - totAd));
         else
           tp[ii[q]] = (float)(-a.cneg * (zb * (2.0 * exA - totAd) - (2.0 * exS - totSd)));
@@ -890,6 +891,7 @@ __device__ __forceinline__ void scan_emit_fast(const SortArgs &a, int p, const S
   }
 }
 
+template <bool DERIV>
 __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
   __shared__ FastShared f;
   const int64_t total = (int64_t)a.nsl * a.G;
@@ -1016,7 +1018,7 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
           const unsigned long long v = ((unsigned long long)kk << 32) | ii;
           for (int j = b; j < e; ++j)
             rank += ((((unsigned long long)f.K[pad8(j)] << 32) | f.I[pad8(j)]) < v) ? 1 : 0;
-          if (a.deriv && (int64_t)ii < a.M) {
+          if (DERIV && (int64_t)ii < a.M) {
             // sources tied with this target; kept in the target's (otherwise zero) weight slot
             float eq = 0.f;
             for (int j = b; j < e; ++j)
@@ -1034,7 +1036,7 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
       continue;
     }
     const SliceParams sp = a.params[p];
-    scan_emit_fast(a, p, sp, eA, f, n, d.e_lo, a.bpre[2 * ((int64_t)p * a.nb + d.b_lo)],
+    scan_emit_fast<DERIV>(a, p, sp, eA, f, n, d.e_lo, a.bpre[2 * ((int64_t)p * a.nb + d.b_lo)],
                    a.bpre[2 * ((int64_t)p * a.nb + d.b_lo) + 1], a.tot[2 * p], a.tot[2 * p + 1], f.sm);
     __syncthreads();
   }
@@ -1077,7 +1079,10 @@ hipError_t launch_sort_path(const ExecArgs &a) {
   const int64_t items = (int64_t)a.nsl * lay.sort_groups;
   const unsigned g4 = (unsigned)std::min<int64_t>(xcd_grid(items), 256 * 2);
   mark(a, ST_SORT_GROUP);
-  sort_fast_kernel<<<g4, kFThreads, 0, a.stream>>>(s);
+  if (a.deriv)
+    sort_fast_kernel<true><<<g4, kFThreads, 0, a.stream>>>(s);
+  else
+    sort_fast_kernel<false><<<g4, kFThreads, 0, a.stream>>>(s);
   mark(a, ST_SORT_FALLBACK);
   sort_fallback_kernel<<<256, 256, 0, a.stream>>>(s);
   return hipGetLastError();

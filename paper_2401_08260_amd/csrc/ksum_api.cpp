@@ -19,7 +19,7 @@ static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
 
 int window_degree_for(int m);
-int nfft_lanes_for(int W);
+int nfft_share_for(int W);
 hipError_t launch_bounds_probe(const ExecArgs &a, double *bounds_out);
 
 static ksum_status fail(ksum_status st, const std::string &msg) {
@@ -105,8 +105,7 @@ static ksum_status validate(int32_t d, int32_t P, ksum_kernel kernel, const ksum
     int lo, cells;
     nfft_window((int)n, resolve_T(kernel, method, p.T), p.window_m, &lo, &cells);
     if (cells > n) return fail(KSUM_EUNSUPPORTED, "NFFT window wider than the grid (T too large)");
-    if ((size_t)cells * 64 * sizeof(float) > 160 * 1024)
-      return fail(KSUM_EUNSUPPORTED, "NFFT window does not fit LDS");
+    if (nfft_share_for(cells) == 0) return fail(KSUM_EUNSUPPORTED, "NFFT window does not fit LDS");
   }
   return KSUM_OK;
 }
@@ -147,8 +146,7 @@ Layout make_layout(const ksum_plan &pl, int64_t N, int64_t M) {
       y.off_fpart = take((size_t)B * y.ndft_chunks * (pl.K + 1) * sizeof(float2));
     } else {
       nfft_window(pl.n_grid, pl.params.T, pl.params.window_m, &y.win_lo, &y.win_cells);
-      const int lanes = nfft_lanes_for(y.win_cells);
-      y.nfft_chunks = (int32_t)((N + (int64_t)lanes * kNfftPPL - 1) / ((int64_t)lanes * kNfftPPL));
+      y.nfft_chunks = (int32_t)((N + (int64_t)256 * kNfftPPL - 1) / ((int64_t)256 * kNfftPPL));
       y.off_fpart = take((size_t)B * y.nfft_chunks * y.win_cells * sizeof(float));
       y.off_grid = take((size_t)B * y.win_cells * sizeof(float));
     }
