@@ -337,7 +337,7 @@ struct AccumArgs {
   int p0;
 };
 
-template <int MW, int DEG>
+template <int MW, int DEG, bool DERIV>
 __global__ __launch_bounds__(256) void nfft_interp_accum_kernel(FourierArgs a, AccumArgs c, int sb) {
   extern __shared__ float G[];   // [sb][W]
   const int64_t per_block = 256 * (int64_t)c.tpt;
@@ -373,16 +373,16 @@ __global__ __launch_bounds__(256) void nfft_interp_accum_kernel(FourierArgs a, A
           float tv = 0.f;
 #pragma unroll
           for (int j = 0; j < 2 * MW; ++j) tv = fmaf(gb[j], tap[j], tv);
-          if (c.dout) tv *= sp.ftau;
+          if (DERIV) tv *= sp.ftau;
           if (c.t2) tv += c.t2[(int64_t)p * a.M + m];
           if (c.t_out) c.t_out[(int64_t)p * a.M + m] = tv;
-          if (c.dout) c.dout[m * c.ldd + c.p0 + p] = tv;
+          if (DERIV) c.dout[m * c.ldd + c.p0 + p] = tv;
           acc[k] += (double)tv;
         }
       }
     }
   }
-  if (c.dout) return;
+  if (DERIV) return;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (k >= c.tpt) break;
@@ -484,8 +484,12 @@ static void launch_interp_m(const FourierArgs &f, const AccumArgs &c, const Exec
   const int sb = std::max(1, std::min(f.nsl, (int)(32768 / (f.W * (int)sizeof(float)))));
   const int64_t nblk = (f.M + 256 * (int64_t)c.tpt - 1) / (256 * (int64_t)c.tpt);
   mark(a, ST_NFFT_INTERP);
-  nfft_interp_accum_kernel<MW, DEG><<<(unsigned)xcd_grid(nblk), 256, (size_t)sb * f.W * sizeof(float),
-                                      a.stream>>>(f, c, sb);
+  if (c.dout)
+    nfft_interp_accum_kernel<MW, DEG, true><<<(unsigned)xcd_grid(nblk), 256, (size_t)sb * f.W * sizeof(float),
+                                               a.stream>>>(f, c, sb);
+  else
+    nfft_interp_accum_kernel<MW, DEG, false><<<(unsigned)xcd_grid(nblk), 256, (size_t)sb * f.W * sizeof(float),
+                                                a.stream>>>(f, c, sb);
 }
 
 hipError_t launch_nfft_interp(const ExecArgs &a, float *s, bool first, bool last) {
