@@ -23,6 +23,73 @@ constexpr int BK = kGemmBK;   // 16
 constexpr int LDA = BK + 4;   // padded LDS row (80 B): conflict-free 16-byte reads per 16 lanes
 constexpr int LDC = BN + 4;   // padded row of the staged output tile
 
+// Epilogue of a 128 x 128 tile, in two halves of 64 slices: the waves holding the
+// half write their accumulators to LDS, then every thread takes 16 values of one
+// row (4 float4 at a stride of 32 columns, so 8 neighbouring threads cover 128
+// contiguous bytes per store), writes them to Z and folds them into the row's
+// min / max.  smem must hold 64 x LDC floats and be free.
+__device__ __forceinline__ void tile_epilogue(const GemmCtl &g, const f32x16 (&acc)[2][2], float *smem,
+                                              uint32_t *smin, uint32_t *smax, int r0, int64_t l0, int64_t L) {
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int lr = lane & 31, lh = lane >> 5;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (wm == h) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            smem[(i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3)) * LDC + wn * 64 + j * 32 + lr] = acc[i][j][r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int lrow = q * 32 + (t >> 3);            // row within the half
+      const int row = r0 + h * 64 + lrow;            // slice within the batch
+      const int c0 = (t & 7) * 4;
+      float vmin = __builtin_huge_valf(), vmax = -__builtin_huge_valf();
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int c = c0 + 32 * k;
+        const float4 v = *reinterpret_cast<const float4 *>(smem + lrow * LDC + c);
+        const int64_t l = l0 + c;
+        if (row < g.nsl) {
+          float *dst = g.Z + (int64_t)row * g.ldz + l;
+          if (g.z_vec4 && l + 3 < L) {
+            *reinterpret_cast<float4 *>(dst) = v;
+          } else {
+            if (l + 0 < L) dst[0] = v.x;
+            if (l + 1 < L) dst[1] = v.y;
+            if (l + 2 < L) dst[2] = v.z;
+            if (l + 3 < L) dst[3] = v.w;
+          }
+        }
+        if (l + 3 < L) {
+          vmin = fminf(vmin, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
+          vmax = fmaxf(vmax, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
+        } else {
+          if (l + 0 < L) { vmin = fminf(vmin, v.x); vmax = fmaxf(vmax, v.x); }
+          if (l + 1 < L) { vmin = fminf(vmin, v.y); vmax = fmaxf(vmax, v.y); }
+          if (l + 2 < L) { vmin = fminf(vmin, v.z); vmax = fmaxf(vmax, v.z); }
+        }
+      }
+#pragma unroll
+      for (int off = 1; off < 8; off <<= 1) {
+        vmin = fminf(vmin, __shfl_xor(vmin, off, 64));
+        vmax = fmaxf(vmax, __shfl_xor(vmax, off, 64));
+      }
+      if ((t & 7) == 0 && row < g.nsl && vmin <= vmax) {
+        atomicMin(&smin[row], float_key(vmin));
+        atomicMax(&smax[row], float_key(vmax));
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Persistent blocks take (point tile, slice tile) work items from a device
 // counter in order, so neighbouring items (the slice tiles of one point tile)
 // run at the same time and every CU ends within about one tile of the others.
@@ -131,65 +198,7 @@ __global__ __launch_bounds__(256) void proj_gemm_kernel(GemmCtl g, PointLoader<I
       __syncthreads();
     }
 
-    // Epilogue, in two halves of 64 slices: the waves holding the half write their
-    // accumulators to LDS, then every thread takes 16 values of one row (4 float4
-    // at a stride of 32 columns, so 8 neighbouring threads cover 128 contiguous
-    // bytes per store), writes them to Z and folds them into the row's min / max.
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (wm == h) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-              smem[(i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3)) * LDC + wn * 64 + j * 32 + lr] = acc[i][j][r];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int lrow = q * 32 + (t >> 3);            // row within the half
-        const int row = r0 + h * 64 + lrow;            // slice within the batch
-        const int c0 = (t & 7) * 4;
-        float vmin = __builtin_huge_valf(), vmax = -__builtin_huge_valf();
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int c = c0 + 32 * k;
-          const float4 v = *reinterpret_cast<const float4 *>(smem + lrow * LDC + c);
-          const int64_t l = l0 + c;
-          if (row < g.nsl) {
-            float *dst = g.Z + (int64_t)row * g.ldz + l;
-            if (g.z_vec4 && l + 3 < ld.L) {
-              *reinterpret_cast<float4 *>(dst) = v;
-            } else {
-              if (l + 0 < ld.L) dst[0] = v.x;
-              if (l + 1 < ld.L) dst[1] = v.y;
-              if (l + 2 < ld.L) dst[2] = v.z;
-              if (l + 3 < ld.L) dst[3] = v.w;
-            }
-          }
-          if (l + 3 < ld.L) {
-            vmin = fminf(vmin, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
-            vmax = fmaxf(vmax, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
-          } else {
-            if (l + 0 < ld.L) { vmin = fminf(vmin, v.x); vmax = fmaxf(vmax, v.x); }
-            if (l + 1 < ld.L) { vmin = fminf(vmin, v.y); vmax = fmaxf(vmax, v.y); }
-            if (l + 2 < ld.L) { vmin = fminf(vmin, v.z); vmax = fmaxf(vmax, v.z); }
-          }
-        }
-#pragma unroll
-        for (int off = 1; off < 8; off <<= 1) {
-          vmin = fminf(vmin, __shfl_xor(vmin, off, 64));
-          vmax = fmaxf(vmax, __shfl_xor(vmax, off, 64));
-        }
-        if ((t & 7) == 0 && row < g.nsl && vmin <= vmax) {
-          atomicMin(&smin[row], float_key(vmin));
-          atomicMax(&smax[row], float_key(vmax));
-        }
-      }
-      __syncthreads();
-    }
+    tile_epilogue(g, acc, smem, smin, smax, r0, l0, ld.L);
   }
   __syncthreads();
   uint32_t *out = g.part + (int64_t)blockIdx.x * g.nsl * 2;

@@ -76,8 +76,12 @@ __device__ __forceinline__ long long fix_s(float v, float z, double cmid, int eS
 }
 
 // ---------------------------------------------------------------------------
-// S1: per (slice, chunk) bucket histogram with fixed-point sums
+// S1: per (slice, chunk) bucket histogram with fixed-point sums.  Each thread
+// loads kHistU projections (and weights) before it touches LDS, so that many
+// loads are in flight per wave.
 // ---------------------------------------------------------------------------
+constexpr int kHistU = 8;
+
 __global__ __launch_bounds__(512) void sort_hist_kernel(SortArgs a) {
   __shared__ uint32_t cnt[2048];
   __shared__ unsigned long long sA[2048], sS[2048];
@@ -95,14 +99,25 @@ __global__ __launch_bounds__(512) void sort_hist_kernel(SortArgs a) {
   const int64_t chunk = (a.L + kSortChunks - 1) / kSortChunks;
   const int64_t l0 = c * chunk, l1 = min(a.L, l0 + chunk);
   const float *Zp = a.Z + (int64_t)p * a.L;
-  for (int64_t l = l0 + threadIdx.x; l < l1; l += blockDim.x) {
-    const float z = Zp[l];
-    const int b = bucket_of(z, sp.fcmin, sp.inv_width, a.nb);
-    atomicAdd(&cnt[b], 1u);
-    if (l >= a.M) {
-      const float v = a.w[l - a.M];
-      atomicAdd(&sA[b], (unsigned long long)fix_a(v, eA));
-      atomicAdd(&sS[b], (unsigned long long)fix_s(v, z, sp.cmid, sp.eS));
+  for (int64_t lb = l0; lb < l1; lb += 512 * kHistU) {
+    float z[kHistU], v[kHistU];
+#pragma unroll
+    for (int u = 0; u < kHistU; ++u) {
+      const int64_t l = lb + threadIdx.x + 512 * u;
+      z[u] = (l < l1) ? Zp[l] : 0.f;
+      v[u] = (l < l1 && l >= a.M) ? a.w[l - a.M] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < kHistU; ++u) {
+      const int64_t l = lb + threadIdx.x + 512 * u;
+      if (l < l1) {
+        const int b = bucket_of(z[u], sp.fcmin, sp.inv_width, a.nb);
+        atomicAdd(&cnt[b], 1u);
+        if (l >= a.M) {
+          atomicAdd(&sA[b], (unsigned long long)fix_a(v[u], eA));
+          atomicAdd(&sS[b], (unsigned long long)fix_s(v[u], z[u], sp.cmid, sp.eS));
+        }
+      }
     }
   }
   __syncthreads();
@@ -193,75 +208,95 @@ __global__ __launch_bounds__(1024) void sort_scan_kernel(SortArgs a) {
 // ---------------------------------------------------------------------------
 // S3: scatter (key, union index) into buckets.  Each tile of kScatTile entries is
 // first ordered by bucket in LDS, so the global writes come as runs of
-// consecutive positions per bucket instead of isolated 8-byte stores.
+// consecutive positions per bucket instead of isolated 8-byte stores.  The next
+// tile's projections are loaded while the current one is processed, the keys
+// stay in registers until they are placed, and the tile counters alternate
+// between two arrays, so a tile takes four barriers plus the one of its scan.
 // ---------------------------------------------------------------------------
 constexpr int kScatTile = 4096;
+constexpr int kScatPer = kScatTile / 512;
 
 __global__ __launch_bounds__(512) void sort_scatter_kernel(SortArgs a) {
   __shared__ unsigned long long tk[kScatTile];
   __shared__ uint16_t tb[kScatTile];
-  __shared__ uint32_t cursor[2048], tcnt[2048], tstart[2048];
-  __shared__ long long sm[64];
+  __shared__ uint32_t cursor[2048], tcnt[2][2048], tstart[2048];
+  __shared__ uint32_t red[8];
   const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * kSortChunks);
   if (work < 0) return;
   const int p = (int)(work / kSortChunks), c = (int)(work % kSortChunks);
   const int64_t base = ((int64_t)p * kSortChunks + c) * a.nb;
-  for (int b = threadIdx.x; b < a.nb; b += blockDim.x) cursor[b] = a.hcnt[base + b];
+  for (int b = threadIdx.x; b < a.nb; b += blockDim.x) {
+    cursor[b] = a.hcnt[base + b];
+    tcnt[0][b] = 0;
+    tcnt[1][b] = 0;
+  }
   const SliceParams sp = a.params[p];
   const int64_t chunk = (a.L + kSortChunks - 1) / kSortChunks;
   const int64_t l0 = c * chunk, l1 = min(a.L, l0 + chunk);
   const float *Zp = a.Z + (int64_t)p * a.L;
   unsigned long long *kp = a.keys + (int64_t)p * a.L;
   const int per = (a.nb + 511) / 512;    // buckets per thread in the scan (<= 4)
-  for (int64_t t0 = l0; t0 < l1; t0 += kScatTile) {
-    const int tn = (int)min((int64_t)kScatTile, l1 - t0);
-    for (int b = threadIdx.x; b < a.nb; b += blockDim.x) tcnt[b] = 0;
-    __syncthreads();
-    // bucket of every entry of the tile; ranks within its bucket
-    int bk[kScatTile / 512];
-    uint32_t rk[kScatTile / 512];
+  float zn[kScatPer];
 #pragma unroll
-    for (int q = 0; q < kScatTile / 512; ++q) {
+  for (int q = 0; q < kScatPer; ++q) {
+    const int64_t l = l0 + threadIdx.x + q * 512;
+    zn[q] = (l < l1) ? Zp[l] : 0.f;
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t t0 = l0; t0 < l1; t0 += kScatTile, buf ^= 1) {
+    const int tn = (int)min((int64_t)kScatTile, l1 - t0);
+    float zc[kScatPer];
+#pragma unroll
+    for (int q = 0; q < kScatPer; ++q) zc[q] = zn[q];
+    if (t0 + kScatTile < l1) {
+#pragma unroll
+      for (int q = 0; q < kScatPer; ++q) {
+        const int64_t l = t0 + kScatTile + threadIdx.x + q * 512;
+        zn[q] = (l < l1) ? Zp[l] : 0.f;
+      }
+    }
+    uint32_t *cntb = tcnt[buf];
+    // bucket of every entry of the tile; ranks within its bucket
+    int bk[kScatPer];
+    uint32_t rk[kScatPer];
+    unsigned long long kv[kScatPer];
+#pragma unroll
+    for (int q = 0; q < kScatPer; ++q) {
       const int i = threadIdx.x + q * 512;
+      bk[q] = 0;
+      rk[q] = 0;
+      kv[q] = 0;
       if (i < tn) {
-        const float z = Zp[t0 + i];
-        const int b = bucket_of(z, sp.fcmin, sp.inv_width, a.nb);
-        bk[q] = b;
-        rk[q] = atomicAdd(&tcnt[b], 1u);
-        tk[i] = (unsigned long long)float_key(z) | ((unsigned long long)(uint32_t)(t0 + i) << 32);
+        bk[q] = bucket_of(zc[q], sp.fcmin, sp.inv_width, a.nb);
+        rk[q] = atomicAdd(&cntb[bk[q]], 1u);
+        kv[q] = (unsigned long long)float_key(zc[q]) | ((unsigned long long)(uint32_t)(t0 + i) << 32);
       }
     }
     __syncthreads();
     // exclusive scan of the tile's bucket counts
-    long long loc = 0;
+    uint32_t loc = 0;
     for (int q = 0; q < per; ++q) {
       const int b = threadIdx.x * per + q;
-      if (b < a.nb) loc += tcnt[b];
+      if (b < a.nb) loc += cntb[b];
     }
-    long long tot;
-    long long ex = block_exclusive_scan(loc, sm, &tot);
+    uint32_t tot;
+    uint32_t ex = block_excl_sum<8>(loc, red, &tot);
     for (int q = 0; q < per; ++q) {
       const int b = threadIdx.x * per + q;
       if (b < a.nb) {
-        tstart[b] = (uint32_t)ex;
-        ex += tcnt[b];
+        tstart[b] = ex;
+        ex += cntb[b];
       }
     }
     __syncthreads();
-    // reorder the tile by bucket in LDS (entries of one bucket stay in tile order)
-    unsigned long long mine[kScatTile / 512];
+    // place the tile in bucket order in LDS (entries of one bucket stay in tile order)
 #pragma unroll
-    for (int q = 0; q < kScatTile / 512; ++q) {
-      const int i = threadIdx.x + q * 512;
-      if (i < tn) mine[q] = tk[i];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kScatTile / 512; ++q) {
+    for (int q = 0; q < kScatPer; ++q) {
       const int i = threadIdx.x + q * 512;
       if (i < tn) {
         const uint32_t pos = tstart[bk[q]] + rk[q];
-        tk[pos] = mine[q];
+        tk[pos] = kv[q];
         tb[pos] = (uint16_t)bk[q];
       }
     }
@@ -272,8 +307,11 @@ __global__ __launch_bounds__(512) void sort_scatter_kernel(SortArgs a) {
       kp[cursor[b] + (uint32_t)i - tstart[b]] = tk[i];
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < a.nb; b += blockDim.x) cursor[b] += tcnt[b];
-    __syncthreads();
+    // the next tile counts into the other array; this one is cleared for the tile after
+    for (int b = threadIdx.x; b < a.nb; b += blockDim.x) {
+      cursor[b] += cntb[b];
+      cntb[b] = 0;
+    }
   }
 }
 
@@ -814,7 +852,8 @@ struct FastShared {
   float W[kFCapPad];
   uint16_t inv[kFCapPad];      // sorted position -> entry (pad8 layout)
   uint32_t cnt[kNS + kNS / 4];
-  double sm[64];
+  double pr[2 * kFWaves];      // wave totals of the (A, S) prefix scan
+  uint32_t cr[kFWaves];        // wave totals of the counter scan
   uint32_t red[2 * kFWaves];
   uint32_t flag;
 };
@@ -838,55 +877,79 @@ __device__ __forceinline__ int sub_bucket(uint32_t key, float zlo, float inv) {
   return (q < (float)kNS) ? (int)q : kNS - 1;
 }
 
+// Per-group scalars the scan needs (bucket prefixes, slice totals, slice
+// parameters), loaded when the group starts so their latency overlaps the sort.
+struct GroupScalars {
+  long long preA, preS, totA, totS;
+  double cmid;
+  int eS;
+};
+
+__device__ __forceinline__ GroupScalars group_scalars(const SortArgs &a, const GroupDesc &d) {
+  GroupScalars s;
+  const int64_t o = 2 * ((int64_t)d.p * a.nb + d.b_lo);
+  s.preA = a.bpre[o];
+  s.preS = a.bpre[o + 1];
+  s.totA = a.tot[2 * d.p];
+  s.totS = a.tot[2 * d.p + 1];
+  s.cmid = a.params[d.p].cmid;
+  s.eS = a.params[d.p].eS;
+  return s;
+}
+
 // Scan of a sorted group: FP64 prefix sums inside the group, taken in its
 // canonical (key, index) order (so the rounding is the same on every run), on
 // top of the exact fixed-point prefix of the group's first bucket.  W holds the
-// weights of the sources (0 for targets).  Thread t owns entries [8t, 8t+8).
+// weights of the sources (0 for targets).  Thread t owns sorted positions
+// [8t, 8t+8); the entries are read from LDS again for the output pass rather
+// than kept in registers.  In derivative mode a target also adds the sources
+// tied with it: the rest of its run of equal keys (targets precede tied sources
+// in the (key, index) order, and a run never crosses a bucket).
 template <bool DERIV>
-__device__ __forceinline__ void scan_emit_fast(const SortArgs &a, int p, const SliceParams &sp, int eA,
-                                               const FastShared &f, int n, int64_t out_pos, long long preA,
-                                               long long preS, long long totA, long long totS, double *smd) {
+__device__ __forceinline__ void scan_emit_fast(const SortArgs &a, int p, const GroupScalars &gs, int eA,
+                                               FastShared &f, int n, int64_t out_pos) {
   const int i0 = threadIdx.x * kFPer;
-  const double sa = ldexp(1.0, -eA), ss = ldexp(1.0, -sp.eS);
-  uint32_t kk[kFPer], ii[kFPer];
-  float ww[kFPer], eqw[kFPer];
   double lA = 0.0, lS = 0.0;
 #pragma unroll
   for (int q = 0; q < kFPer; ++q) {
     const int j = i0 + q;
-    kk[q] = 0;
-    ii[q] = 0;
-    ww[q] = 0.f;
-    eqw[q] = 0.f;
     if (j < n) {
       const int e = pad8(f.inv[pad8(j)]);
-      kk[q] = f.K[e];
-      ii[q] = f.I[e];
-      ww[q] = ((int64_t)ii[q] >= a.M) ? f.W[e] : 0.f;
-      if (DERIV && (int64_t)ii[q] < a.M) eqw[q] = f.W[e];
-      lA += (double)ww[q];
-      lS += (double)ww[q] * ((double)key_float(kk[q]) - sp.cmid);
+      const double v = (double)f.W[e];
+      lA += v;
+      lS += v * ((double)key_float(f.K[e]) - gs.cmid);
     }
   }
-  double tA, tS;
-  double exA = block_exclusive_scan(lA, smd, &tA) + (double)preA * sa;
-  double exS = block_exclusive_scan(lS, smd, &tS) + (double)preS * ss;
-  const double totAd = (double)totA * sa, totSd = (double)totS * ss;
+  double gA, gS;
+  block_excl_sum2<kFWaves>(lA, lS, f.pr, &gA, &gS);
+  const double sa = ldexp(1.0, -eA), ss = ldexp(1.0, -gs.eS);
+  double exA = lA + (double)gs.preA * sa, exS = lS + (double)gs.preS * ss;
+  const double totAd = (double)gs.totA * sa, totSd = (double)gs.totS * ss;
   float *tp = a.t + (int64_t)p * a.M;
 #pragma unroll
   for (int q = 0; q < kFPer; ++q) {
     const int j = i0 + q;
     if (j < n) {
-      const double zb = (double)key_float(kk[q]) - sp.cmid;
-      if ((int64_t)ii[q] < a.M) {
-        if (DERIV)
-          tp[ii[q]] = (float)(-a.cneg * (2.0 * exA + (double)eqw[q] - totAd));
-        else
-          tp[ii[q]] = (float)(-a.cneg * (zb * (2.0 * exA - totAd) - (2.0 * exS - totSd)));
+      const int e = pad8(f.inv[pad8(j)]);
+      const uint32_t kk = f.K[e], ii = f.I[e];
+      const double v = (double)f.W[e];
+      const double zb = (double)key_float(kk) - gs.cmid;
+      if ((int64_t)ii < a.M) {
+        if (DERIV) {
+          double eq = 0.0;
+          for (int j2 = j + 1; j2 < n; ++j2) {
+            const int e2 = pad8(f.inv[pad8(j2)]);
+            if (f.K[e2] != kk) break;
+            eq += (double)f.W[e2];
+          }
+          tp[ii] = (float)(-a.cneg * (2.0 * exA + eq - totAd));
+        } else {
+          tp[ii] = (float)(-a.cneg * (zb * (2.0 * exA - totAd) - (2.0 * exS - totSd)));
+        }
       }
-      if (a.perm) a.perm[(int64_t)p * a.L + out_pos + j] = (int32_t)ii[q];
-      exA += (double)ww[q];
-      exS += (double)ww[q] * zb;
+      if (a.perm) a.perm[(int64_t)p * a.L + out_pos + j] = (int32_t)ii;
+      exA += v;
+      exS += v * zb;
     }
   }
 }
@@ -900,12 +963,14 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
   const int64_t per_x = (total + 7) / 8;
   const int64_t lo = x * per_x, hi = min(total, lo + per_x);
   int64_t item = lo + r;
-  GroupDesc nd{};
+  // descriptors run two items ahead of the keys, the keys one item ahead of the sort
+  GroupDesc nd{}, nd2{};
   unsigned long long nk[kFPer];
   if (item < hi) {
     nd = group_desc(a, item);
     load_group_keys(a, nd, nk);
   }
+  if (item + gx < hi) nd2 = group_desc(a, item + gx);
   const int eA = (int)a.misc[1];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   while (item < hi) {
@@ -915,8 +980,9 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
     for (int q = 0; q < kFPer; ++q) kc[q] = nk[q];
     const int64_t next = item + gx;
     if (next < hi) {
-      nd = group_desc(a, next);
+      nd = nd2;
       load_group_keys(a, nd, nk);
+      if (next + gx < hi) nd2 = group_desc(a, next + gx);
     }
     const int64_t cur_item = item;
     item = next;
@@ -926,6 +992,7 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
       continue;
     }
     const int n = d.n, p = d.p;
+    const GroupScalars gs = group_scalars(a, d);
     // weights of the sources, gathered now and used at the scatter
     float wv[kFPer];
 #pragma unroll
@@ -933,7 +1000,7 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
       const uint32_t idx = (uint32_t)(kc[q] >> 32);
       wv[q] = (threadIdx.x + kFThreads * q < n && (int64_t)idx >= a.M) ? a.w[idx - a.M] : 0.f;
     }
-    // key range of the group
+    // key range of the group (padding keys are ~0 in the low word: excluded from the max)
     uint32_t kmin = 0xffffffffu, kmax = 0u;
 #pragma unroll
     for (int q = 0; q < kFPer; ++q) {
@@ -942,10 +1009,8 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
         kmax = max(kmax, (uint32_t)kc[q]);
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off, 64));
-      kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off, 64));
-    }
+    kmin = wave_min_u32(kmin);
+    kmax = wave_max_u32(kmax);
     if (lane == 0) {
       f.red[wid] = kmin;
       f.red[kFWaves + wid] = kmax;
@@ -955,6 +1020,7 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
     __syncthreads();
     kmin = f.red[0];
     kmax = f.red[kFWaves];
+#pragma unroll
     for (int w2 = 1; w2 < kFWaves; ++w2) {
       kmin = min(kmin, f.red[w2]);
       kmax = max(kmax, f.red[kFWaves + w2]);
@@ -967,22 +1033,25 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
       continue;
     }
     const float inv = (float)inv_d;
+    int sb[kFPer];
 #pragma unroll
-    for (int q = 0; q < kFPer; ++q)
-      if (threadIdx.x + kFThreads * q < n) atomicAdd(&f.cnt[pad4(sub_bucket((uint32_t)kc[q], zlo, inv))], 1u);
+    for (int q = 0; q < kFPer; ++q) {
+      sb[q] = sub_bucket((uint32_t)kc[q], zlo, inv);
+      if (threadIdx.x + kFThreads * q < n) atomicAdd(&f.cnt[pad4(sb[q])], 1u);
+    }
     __syncthreads();
     {
       // exclusive scan of the counters, 4 consecutive per thread (stride 5 words)
       constexpr int per = kNS / kFThreads;
       uint32_t loc[per];
-      double sum = 0.0;
+      uint32_t sum = 0;
 #pragma unroll
       for (int q = 0; q < per; ++q) {
         loc[q] = f.cnt[pad4(threadIdx.x * per + q)];
-        sum += (double)loc[q];
+        sum += loc[q];
       }
-      double tot;
-      uint32_t ex = (uint32_t)block_exclusive_scan(sum, f.sm, &tot);
+      uint32_t tot;
+      uint32_t ex = block_excl_sum<kFWaves>(sum, f.cr, &tot);
 #pragma unroll
       for (int q = 0; q < per; ++q) {
         f.cnt[pad4(threadIdx.x * per + q)] = ex;
@@ -993,7 +1062,7 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
 #pragma unroll
     for (int q = 0; q < kFPer; ++q) {
       if (threadIdx.x + kFThreads * q < n) {
-        const int pos = pad8((int)atomicAdd(&f.cnt[pad4(sub_bucket((uint32_t)kc[q], zlo, inv))], 1u));
+        const int pos = pad8((int)atomicAdd(&f.cnt[pad4(sb[q])], 1u));
         f.K[pos] = (uint32_t)kc[q];
         f.I[pos] = (uint32_t)(kc[q] >> 32);
         f.W[pos] = wv[q];
@@ -1008,9 +1077,9 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
       const int i = threadIdx.x + kFThreads * q;
       if (i < n) {
         const uint32_t kk = f.K[pad8(i)], ii = f.I[pad8(i)];
-        const int sb = sub_bucket(kk, zlo, inv);
-        const int e = (int)f.cnt[pad4(sb)];
-        const int b = sb ? (int)f.cnt[pad4(sb - 1)] : 0;
+        const int s = sub_bucket(kk, zlo, inv);
+        const int e = (int)f.cnt[pad4(s)];
+        const int b = s ? (int)f.cnt[pad4(s - 1)] : 0;
         int rank = 0;
         if (e - b > kSubRunMax) {
           f.flag = 1;
@@ -1018,13 +1087,6 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
           const unsigned long long v = ((unsigned long long)kk << 32) | ii;
           for (int j = b; j < e; ++j)
             rank += ((((unsigned long long)f.K[pad8(j)] << 32) | f.I[pad8(j)]) < v) ? 1 : 0;
-          if (DERIV && (int64_t)ii < a.M) {
-            // sources tied with this target; kept in the target's (otherwise zero) weight slot
-            float eq = 0.f;
-            for (int j = b; j < e; ++j)
-              if (f.K[pad8(j)] == kk && (int64_t)f.I[pad8(j)] >= a.M) eq += f.W[pad8(j)];
-            f.W[pad8(i)] = eq;
-          }
         }
         f.inv[pad8(min(b + rank, kSortCap - 1))] = (uint16_t)i;
       }
@@ -1035,9 +1097,7 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
       push_fallback(a, cur_item);
       continue;
     }
-    const SliceParams sp = a.params[p];
-    scan_emit_fast<DERIV>(a, p, sp, eA, f, n, d.e_lo, a.bpre[2 * ((int64_t)p * a.nb + d.b_lo)],
-                   a.bpre[2 * ((int64_t)p * a.nb + d.b_lo) + 1], a.tot[2 * p], a.tot[2 * p + 1], f.sm);
+    scan_emit_fast<DERIV>(a, p, gs, eA, f, n, d.e_lo);
     __syncthreads();
   }
 }
