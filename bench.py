@@ -107,6 +107,29 @@ WORKLOAD_TAG = {"negdist": "negdist_N1e5_d784_P256", "laplace": "laplace_N2e5_d3
                 "gauss_nfft": "gauss_nfft_N1e6_d50_P256", "gauss_ndft": "gauss_ndft_N1e3_d10_P64"}
 
 
+def measure_stream_peak(dev, nbytes=1 << 30, reps=5):
+    """Copy bandwidth of this GPU: best of `reps` device-to-device copies of `nbytes`
+    (read + write counted), timed with events.  The reference that the HBM-bound
+    stages are measured against next to the nominal peak."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3
+        best = t if best is None else min(best, t)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBps": 2 * nbytes / best / 1e9, "bytes": nbytes, "reps": reps, "kind": "device-to-device copy"}
+
+
 def source_digest(fname):
     import hashlib
     h = hashlib.sha256()
@@ -496,6 +519,25 @@ def main():
                 "traffic_detail": tr, "avg_launch_ms": stage_ms[dom],
                 "share_of_step": stage_share[dom] / ms}
 
+    # every stage against its roofline: algorithmic bytes (or flops) per launch over the
+    # launch time, and for HBM-bound stages the measured HBM traffic over the same time,
+    # as fractions of the nominal peak and of the copy bandwidth measured here
+    stream_pk = measure_stream_peak(dev)
+    stage_roofline = {}
+    for k in stage_share:
+        kw = kernel_work(k, wl, wl.P)
+        if not kw:
+            continue
+        b, amt, u, pk = kw
+        ach = amt / (stage_ms[k] * 1e-3)
+        ent = {"bound": b, "avg_launch_ms": stage_ms[k], "achieved": ach, "unit": u, "frac_peak": ach / pk}
+        trk = measured_traffic(wl.name, k)
+        if b == "hbm" and trk:
+            gbs = trk["total_GB"] / (stage_ms[k] * 1e-3)
+            ent.update(measured_GBps=gbs, frac_peak_measured=gbs / PEAK_HBM_GBS,
+                       frac_stream_measured=gbs / stream_pk["GBps"])
+        stage_roofline[k] = ent
+
     # timed region 3: the same step with the split-BF16 projection ("mixed")
     mixed = None
     s_mixed = None
@@ -535,6 +577,8 @@ def main():
                    "input": wl.dtype, "sigma": sigma},
         "stage_ms_per_step": stage_share,
         "roofline": roofline,
+        "stream_peak": stream_pk,
+        "stage_roofline": stage_roofline,
         "mixed": mixed,
     }
 

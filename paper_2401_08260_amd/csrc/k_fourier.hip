@@ -213,25 +213,49 @@ __global__ __launch_bounds__(256) void nfft_spread_kernel(FourierArgs a) {
   const int64_t chunk = (int64_t)256 * kNfftPPL;
   const int64_t n0 = (int64_t)c * chunk, n1 = min(a.N, n0 + chunk);
   const float fn = (float)a.n;
-  for (int64_t i = n0 + t; i < n1; i += 256) {
-    const float xt = (Zx[i] - sp.fcmin) * sp.ftau + sp.shift;
-    const float u = xt * fn;
-    int i0 = (int)floorf(u);
-    const float fr = u - (float)i0;
-    i0 = min(max(i0, a.i0min), a.i0max);
-    float tap[2 * MW];
-    window_taps<MW, DEG>(a.poly, fr - 0.5f, tap);
-    const float wv = a.w[i];
-    // the 2 MW cells of this lane's copy are distinct: read them all, then write
-    float *base = acc + (i0 - MW + 1 - a.lo) * NC + copy;
+  // sources in batches of kSU per thread; the next batch's projections and weights
+  // are loaded while the current one is spread
+  constexpr int kSU = 4;
+  float zn[kSU], wn[kSU];
+  auto load = [&](int64_t i, float (&z)[kSU], float (&w)[kSU]) {
+#pragma unroll
+    for (int u = 0; u < kSU; ++u) {
+      const int64_t iu = i + 256 * u;
+      z[u] = iu < n1 ? Zx[iu] : 0.f;
+      w[u] = iu < n1 ? a.w[iu] : 0.f;
+    }
+  };
+  load(n0 + t, zn, wn);
+  for (int64_t ib = n0 + t; ib < n1; ib += 256 * kSU) {
+    float zc[kSU], wc[kSU];
+#pragma unroll
+    for (int u = 0; u < kSU; ++u) {
+      zc[u] = zn[u];
+      wc[u] = wn[u];
+    }
+    if (ib + 256 * kSU < n1) load(ib + 256 * kSU, zn, wn);
+#pragma unroll
+    for (int u = 0; u < kSU; ++u) {
+      if (ib + 256 * u >= n1) break;
+      const float xt = (zc[u] - sp.fcmin) * sp.ftau + sp.shift;
+      const float uu = xt * fn;
+      int i0 = (int)floorf(uu);
+      const float fr = uu - (float)i0;
+      i0 = min(max(i0, a.i0min), a.i0max);
+      float tap[2 * MW];
+      window_taps<MW, DEG>(a.poly, fr - 0.5f, tap);
+      const float wv = wc[u];
+      // the 2 MW cells of this lane's copy are distinct: read them all, then write
+      float *base = acc + (i0 - MW + 1 - a.lo) * NC + copy;
 #pragma unroll 1
-    for (int ph = 0; ph < SH; ++ph) {
-      if (phase == ph) {
-        float v[2 * MW];
+      for (int ph = 0; ph < SH; ++ph) {
+        if (phase == ph) {
+          float v[2 * MW];
 #pragma unroll
-        for (int j = 0; j < 2 * MW; ++j) v[j] = base[j * NC];
+          for (int j = 0; j < 2 * MW; ++j) v[j] = base[j * NC];
 #pragma unroll
-        for (int j = 0; j < 2 * MW; ++j) base[j * NC] = fmaf(wv, tap[j], v[j]);
+          for (int j = 0; j < 2 * MW; ++j) base[j * NC] = fmaf(wv, tap[j], v[j]);
+        }
       }
     }
   }
@@ -320,8 +344,8 @@ __global__ __launch_bounds__(256) void nfft_grid_kernel(FourierArgs a) {
 }
 
 // Interpolation at the targets fused with the slice average (Algorithm
-// "Sliced Fast Fourier Summation", last step): every block owns a range of
-// targets, stages the grid windows of a sub-batch of slices in LDS and adds
+// "Sliced Fast Fourier Summation", last step): every block owns 256 targets,
+// stages the grid windows of a sub-batch of slices in LDS and adds
 // t_{m,p} (plus the sorted part t2 of the Laplacian) over the slices in order in
 // FP64, so t never goes through HBM.  Optionally writes the per-slice t (probe).
 struct AccumArgs {
@@ -331,68 +355,86 @@ struct AccumArgs {
   float *t_out;           // [nsl][M] per-slice sums (probe) or null
   int first, last;
   double invP;
-  int tpt;                // targets per thread
   float *dout;            // derivative mode: dout[m * ldd + p0 + p] = tau t'(y~) + t2, no average
   int64_t ldd;
   int p0;
 };
 
+// One target per thread.  A block stages the grid windows and the rescaling of a
+// sub-batch of sb slices in LDS (8 loads in flight per thread), and each thread
+// loads the projections (and t2) of kIU slices before it evaluates them, so that
+// several loads are in flight.
+constexpr int kIU = 4;
+
 template <int MW, int DEG, bool DERIV>
 __global__ __launch_bounds__(256) void nfft_interp_accum_kernel(FourierArgs a, AccumArgs c, int sb) {
-  extern __shared__ float G[];   // [sb][W]
-  const int64_t per_block = 256 * (int64_t)c.tpt;
-  const int64_t nblk = (a.M + per_block - 1) / per_block;
+  extern __shared__ float G[];   // [sb][W] window values, then [sb][3] (fcmin, ftau, shift)
+  const int64_t nblk = (a.M + 255) / 256;
   const int64_t work = xcd_remap(blockIdx.x, nblk);
   if (work < 0) return;
-  const int64_t m0 = work * per_block;
+  const int64_t m = work * 256 + threadIdx.x;
+  const bool live = m < a.M;
   const float fn = (float)a.n;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  float *SP = G + (size_t)sb * a.W;
+  double acc = 0.0;
   for (int pb = 0; pb < a.nsl; pb += sb) {
     const int np = min(sb, a.nsl - pb);
     __syncthreads();
-    for (int i = threadIdx.x; i < np * a.W; i += blockDim.x) G[i] = a.gwin[(int64_t)pb * a.W + i];
+    const int nw = np * a.W;
+    const float *gsrc = a.gwin + (int64_t)pb * a.W;
+    for (int i0 = threadIdx.x; i0 < nw; i0 += 256 * 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (i0 + 256 * u < nw) ? gsrc[i0 + 256 * u] : 0.f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + 256 * u < nw) G[i0 + 256 * u] = v[u];
+    }
+    for (int q = threadIdx.x; q < np; q += blockDim.x) {
+      const SliceParams sp = a.params[pb + q];
+      SP[3 * q] = sp.fcmin;
+      SP[3 * q + 1] = sp.ftau;
+      SP[3 * q + 2] = sp.shift;
+    }
     __syncthreads();
-    for (int q = 0; q < np; ++q) {
-      const int p = pb + q;
-      const SliceParams sp = a.params[p];
-      const float *Zy = a.Z + (int64_t)p * a.L;
-      const float *Gp = G + q * a.W;
+    for (int q0 = 0; q0 < np; q0 += kIU) {
+      float zv[kIU], t2v[kIU];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (k >= c.tpt) break;
-        const int64_t m = m0 + threadIdx.x + 256 * k;
-        if (m < a.M) {
-          const float yt = (Zy[m] - sp.fcmin) * sp.ftau + sp.shift;
-          const float u = yt * fn;
-          int i0 = (int)floorf(u);
-          const float fr = u - (float)i0;
-          i0 = min(max(i0, a.i0min), a.i0max);
-          float tap[2 * MW];
-          window_taps<MW, DEG>(a.poly, fr - 0.5f, tap);
-          const float *gb = Gp + (i0 - MW + 1 - a.lo);
-          float tv = 0.f;
+      for (int u = 0; u < kIU; ++u) {
+        const int p = pb + q0 + u;
+        const bool ok = live && q0 + u < np;
+        zv[u] = ok ? a.Z[(int64_t)p * a.L + m] : 0.f;
+        t2v[u] = (ok && c.t2) ? c.t2[(int64_t)p * a.M + m] : 0.f;
+      }
 #pragma unroll
-          for (int j = 0; j < 2 * MW; ++j) tv = fmaf(gb[j], tap[j], tv);
-          if (DERIV) tv *= sp.ftau;
-          if (c.t2) tv += c.t2[(int64_t)p * a.M + m];
-          if (c.t_out) c.t_out[(int64_t)p * a.M + m] = tv;
-          if (DERIV) c.dout[m * c.ldd + c.p0 + p] = tv;
-          acc[k] += (double)tv;
-        }
+      for (int u = 0; u < kIU; ++u) {
+        const int q = q0 + u;
+        if (q >= np || !live) break;
+        const int p = pb + q;
+        const float ftau = SP[3 * q + 1];
+        const float yt = (zv[u] - SP[3 * q]) * ftau + SP[3 * q + 2];
+        const float uu = yt * fn;
+        int i0 = (int)floorf(uu);
+        const float fr = uu - (float)i0;
+        i0 = min(max(i0, a.i0min), a.i0max);
+        float tap[2 * MW];
+        window_taps<MW, DEG>(a.poly, fr - 0.5f, tap);
+        const float *gb = G + q * a.W + (i0 - MW + 1 - a.lo);
+        float tv = 0.f;
+#pragma unroll
+        for (int j = 0; j < 2 * MW; ++j) tv = fmaf(gb[j], tap[j], tv);
+        if (DERIV) tv *= ftau;
+        tv += t2v[u];
+        if (c.t_out) c.t_out[(int64_t)p * a.M + m] = tv;
+        if (DERIV) c.dout[m * c.ldd + c.p0 + p] = tv;
+        acc += (double)tv;
       }
     }
   }
-  if (DERIV) return;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (k >= c.tpt) break;
-    const int64_t m = m0 + threadIdx.x + 256 * k;
-    if (m < a.M) {
-      const double v = (c.first ? 0.0 : c.sacc[m]) + acc[k];
-      if (c.last) c.s[m] = (float)(v * c.invP);
-      else c.sacc[m] = v;
-    }
-  }
+  if (DERIV || !live) return;
+  const double v = (c.first ? 0.0 : c.sacc[m]) + acc;
+  if (c.last) c.s[m] = (float)(v * c.invP);
+  else c.sacc[m] = v;
 }
 
 template <int MW, int DEG, int SH>
@@ -481,15 +523,14 @@ hipError_t launch_nfft(const ExecArgs &a) {
 
 template <int MW, int DEG>
 static void launch_interp_m(const FourierArgs &f, const AccumArgs &c, const ExecArgs &a) {
-  const int sb = std::max(1, std::min(f.nsl, (int)(32768 / (f.W * (int)sizeof(float)))));
-  const int64_t nblk = (f.M + 256 * (int64_t)c.tpt - 1) / (256 * (int64_t)c.tpt);
+  const unsigned grid = (unsigned)xcd_grid((f.M + 255) / 256);
+  const int sb = std::max(1, std::min(f.nsl, (int)(32768 / ((f.W + 3) * (int)sizeof(float)))));
+  const size_t lds = (size_t)sb * (f.W + 3) * sizeof(float);
   mark(a, ST_NFFT_INTERP);
   if (c.dout)
-    nfft_interp_accum_kernel<MW, DEG, true><<<(unsigned)xcd_grid(nblk), 256, (size_t)sb * f.W * sizeof(float),
-                                               a.stream>>>(f, c, sb);
+    nfft_interp_accum_kernel<MW, DEG, true><<<grid, 256, lds, a.stream>>>(f, c, sb);
   else
-    nfft_interp_accum_kernel<MW, DEG, false><<<(unsigned)xcd_grid(nblk), 256, (size_t)sb * f.W * sizeof(float),
-                                                a.stream>>>(f, c, sb);
+    nfft_interp_accum_kernel<MW, DEG, false><<<grid, 256, lds, a.stream>>>(f, c, sb);
 }
 
 hipError_t launch_nfft_interp(const ExecArgs &a, float *s, bool first, bool last) {
@@ -504,7 +545,6 @@ hipError_t launch_nfft_interp(const ExecArgs &a, float *s, bool first, bool last
   c.first = first ? 1 : 0;
   c.last = last ? 1 : 0;
   c.invP = 1.0 / (double)pl.P;
-  c.tpt = (int)std::max<int64_t>(1, std::min<int64_t>(4, lay.M / (256 * 1024)));
   c.dout = a.deriv ? a.dout : nullptr;
   c.ldd = a.ldd;
   c.p0 = a.p0;
