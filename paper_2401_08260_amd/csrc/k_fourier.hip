@@ -362,9 +362,9 @@ struct AccumArgs {
 
 // One target per thread.  A block stages the grid windows and the rescaling of a
 // sub-batch of sb slices in LDS (8 loads in flight per thread), and each thread
-// loads the projections (and t2) of kIU slices before it evaluates them, so that
-// several loads are in flight.
-constexpr int kIU = 4;
+// loads the projections (and t2) of the next kIU slices while it evaluates the
+// current ones, so that many loads are in flight.
+constexpr int kIU = 8;
 
 template <int MW, int DEG, bool DERIV>
 __global__ __launch_bounds__(256) void nfft_interp_accum_kernel(FourierArgs a, AccumArgs c, int sb) {
@@ -397,15 +397,27 @@ __global__ __launch_bounds__(256) void nfft_interp_accum_kernel(FourierArgs a, A
       SP[3 * q + 2] = sp.shift;
     }
     __syncthreads();
-    for (int q0 = 0; q0 < np; q0 += kIU) {
-      float zv[kIU], t2v[kIU];
+    // batches of kIU slices; the loads of the next batch are issued before the
+    // current one is evaluated
+    float zn[kIU], t2n[kIU];
+    auto load = [&](int q0, float (&z)[kIU], float (&t2)[kIU]) {
 #pragma unroll
       for (int u = 0; u < kIU; ++u) {
         const int p = pb + q0 + u;
         const bool ok = live && q0 + u < np;
-        zv[u] = ok ? a.Z[(int64_t)p * a.L + m] : 0.f;
-        t2v[u] = (ok && c.t2) ? c.t2[(int64_t)p * a.M + m] : 0.f;
+        z[u] = ok ? a.Z[(int64_t)p * a.L + m] : 0.f;
+        t2[u] = (ok && c.t2) ? c.t2[(int64_t)p * a.M + m] : 0.f;
       }
+    };
+    load(0, zn, t2n);
+    for (int q0 = 0; q0 < np; q0 += kIU) {
+      float zv[kIU], t2v[kIU];
+#pragma unroll
+      for (int u = 0; u < kIU; ++u) {
+        zv[u] = zn[u];
+        t2v[u] = t2n[u];
+      }
+      if (q0 + kIU < np) load(q0 + kIU, zn, t2n);
 #pragma unroll
       for (int u = 0; u < kIU; ++u) {
         const int q = q0 + u;
