@@ -226,3 +226,23 @@ def test_matern_reduced():
     note(f"  rel err {err:.3e}")
     assert err <= TOL
     assert sliced.rel_l2(r["t"].astype(np.float64), ts) <= TOL
+
+
+def test_laplace_many_slices_batched_ragged():
+    """Laplacian (NFFT + sort) with P = 70 in slice batches of 32 (so 32, 32, 6), ragged
+    N and M: more slices than one LDS sub-batch of the interpolation holds for this
+    window (57), batches of 8 slices with a partial last one, and the running sum
+    across slice batches.  Per-slice sums and the average against the oracle."""
+    rng = np.random.default_rng(70)
+    N, M, d, P = 1500, 700, 48, 70
+    x = rng.random((N, d), dtype=np.float32)
+    y = rng.random((M, d), dtype=np.float32)
+    w = rng.random(N).astype(np.float32)
+    sigma = float(np.sqrt(d / 6.0))
+    note(f"laplace batched N={N} M={M} d={d} P={P}")
+    r = run_gpu("laplacian", x, y, w, P, seed=11, sigma=sigma, n_coeff=256, T=0.125, slice_batch=32, probe=True)
+    ref, ts = oracle_s("laplacian", x, y, w, r["xi"], sigma, "nfft", 256, 0.125, slices=True)
+    err = sliced.rel_l2(r["s"], ref)
+    note(f"  rel err {err:.3e}")
+    assert err <= TOL
+    assert sliced.rel_l2(r["t"].astype(np.float64), ts) <= TOL
