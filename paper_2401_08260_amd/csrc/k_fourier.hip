@@ -195,7 +195,7 @@ __device__ __forceinline__ void window_taps(const WindowPoly &wp, float x, float
 // update it one after the other (SH phases in lane order), so every copy sees its
 // updates in a fixed order and the result is deterministic.  SH grows with the
 // window so that wide windows (the Laplacian's and Matern's T = 1/8) still leave
-// room for several blocks per CU.
+// room for two blocks per CU.
 template <int MW, int DEG, int SH>
 __global__ __launch_bounds__(256) void nfft_spread_kernel(FourierArgs a) {
   extern __shared__ float acc[];   // [W][NC]
@@ -480,11 +480,12 @@ static void launch_nfft_m(const FourierArgs &f, const ExecArgs &a) {
 }
 
 // Lanes per window copy of the spread: the smallest power of two that keeps a
-// 256-thread block's copies within 40 KB (several blocks per CU); 0 if even 64
-// lanes per copy (4 copies) do not fit 64 KB.
+// 256-thread block's copies within 80 KB (two blocks per CU: fewer ordered phases
+// pay more than a third and fourth block would); 0 if even 64 lanes per copy (4
+// copies) do not fit 64 KB.
 int nfft_share_for(int W) {
   for (int sh = 1; sh <= 64; sh <<= 1)
-    if ((size_t)W * (256 / sh) * sizeof(float) <= 40 * 1024) return sh;
+    if ((size_t)W * (256 / sh) * sizeof(float) <= 80 * 1024) return sh;
   return ((size_t)W * 4 * sizeof(float) <= 64 * 1024) ? 64 : 0;
 }
 
