@@ -23,7 +23,7 @@ constexpr int kGemmBM = 128;        // slices per GEMM tile (P is padded to it)
 constexpr int kGemmBlocksPerCU = 3; // persistent projection blocks per CU
 constexpr int kMaxBatch = 1024;     // slices per batch (per-block min / max live in LDS)
 constexpr int kSortChunks = 16;     // chunks per slice in the bucket histogram / scatter
-constexpr int kNfftPPL = 64;        // sources per lane in an NFFT spread block
+constexpr int kNfftPPL = 128;       // sources per lane in an NFFT spread block
 constexpr int kSortCap = 4096;      // elements a bucket group may hold to be sorted in LDS
 constexpr int kSortHalf = kSortCap / 2;
 
