@@ -144,6 +144,28 @@ __global__ __launch_bounds__(256) void proj_gemm_kernel(GemmCtl g, PointLoader<I
       *reinterpret_cast<float4 *>(S + row * LDA + k4) = v;
     };
 
+    // fragments of one half of a lane's 8 contraction indices (its first or last 4) in buffer b
+    auto frag = [&](int b, int half, float4 (&fa)[2], float4 (&fb)[2]) {
+      const float *pa = As(b) + (wm * 64 + lr) * LDA + lh * 8 + half * 4;
+      const float *pb = Bs(b) + (wn * 64 + lr) * LDA + lh * 8 + half * 4;
+      fa[0] = *reinterpret_cast<const float4 *>(pa);
+      fa[1] = *reinterpret_cast<const float4 *>(pa + 32 * LDA);
+      fb[0] = *reinterpret_cast<const float4 *>(pb);
+      fb[1] = *reinterpret_cast<const float4 *>(pb + 32 * LDA);
+    };
+    // the 16 MFMAs of one half: 4 contraction steps x 2 x 2 blocks of 32 x 32
+    auto mfma_half = [&](const float4 (&fa)[2], const float4 (&fb)[2]) {
+      const float av[2][4] = {{fa[0].x, fa[0].y, fa[0].z, fa[0].w}, {fa[1].x, fa[1].y, fa[1].z, fa[1].w}};
+      const float bv[2][4] = {{fb[0].x, fb[0].y, fb[0].z, fb[0].w}, {fb[1].x, fb[1].y, fb[1].z, fb[1].w}};
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i][s], bv[j][s], acc[i][j], 0, 0, 0);
+    };
+
     float4 ra0 = load_a(0, t), ra1 = load_a(0, t + 256);
     float4 rb0 = ld.load1(l0, 0, t), rb1 = ld.load1(l0, 0, t + 256);
     store4(As(0), t, ra0);
@@ -151,53 +173,45 @@ __global__ __launch_bounds__(256) void proj_gemm_kernel(GemmCtl g, PointLoader<I
     store4(Bs(0), t, rb0);
     store4(Bs(0), t + 256, rb1);
     __syncthreads();
+    if (nk > 1) {
+      ra0 = load_a(BK, t);
+      ra1 = load_a(BK, t + 256);
+      rb0 = ld.load1(l0, BK, t);
+      rb1 = ld.load1(l0, BK, t + 256);
+    }
+    float4 flo_a[2], flo_b[2], fhi_a[2], fhi_b[2];
+    frag(0, 0, flo_a, flo_b);
 
+    // Software pipeline over the K-blocks, so that no wave waits for LDS while
+    // all waves of the CU read it at once: at the top of iteration kb the first
+    // half's fragments of kb are in flight and the loads of K-block kb + 1 are in
+    // registers.  The first half's MFMAs overlap the second half's reads; the
+    // next block goes to the other buffer; after the barrier the next block's
+    // first-half reads and loads two blocks ahead overlap the second half's MFMAs.
     for (int kb = 0; kb < nk; ++kb) {
       const int cur = kb & 1;
-      const bool more = kb + 1 < nk;
-      if (more) {
-        ra0 = load_a((kb + 1) * BK, t);
-        ra1 = load_a((kb + 1) * BK, t + 256);
-        rb0 = ld.load1(l0, (kb + 1) * BK, t);
-        rb1 = ld.load1(l0, (kb + 1) * BK, t + 256);
-      }
-      const float *pa0 = As(cur) + (wm * 64 + lr) * LDA + lh * 8;
-      const float *pb0 = Bs(cur) + (wn * 64 + lr) * LDA + lh * 8;
-      const float4 alo0 = *reinterpret_cast<const float4 *>(pa0);
-      const float4 alo1 = *reinterpret_cast<const float4 *>(pa0 + 32 * LDA);
-      const float4 blo0 = *reinterpret_cast<const float4 *>(pb0);
-      const float4 blo1 = *reinterpret_cast<const float4 *>(pb0 + 32 * LDA);
-      const float4 ahi0 = *reinterpret_cast<const float4 *>(pa0 + 4);
-      const float4 ahi1 = *reinterpret_cast<const float4 *>(pa0 + 32 * LDA + 4);
-      const float4 bhi0 = *reinterpret_cast<const float4 *>(pb0 + 4);
-      const float4 bhi1 = *reinterpret_cast<const float4 *>(pb0 + 32 * LDA + 4);
-      const float al[2][4] = {{alo0.x, alo0.y, alo0.z, alo0.w}, {alo1.x, alo1.y, alo1.z, alo1.w}};
-      const float bl[2][4] = {{blo0.x, blo0.y, blo0.z, blo0.w}, {blo1.x, blo1.y, blo1.z, blo1.w}};
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(al[i][s], bl[j][s], acc[i][j], 0, 0, 0);
-      const float ah[2][4] = {{ahi0.x, ahi0.y, ahi0.z, ahi0.w}, {ahi1.x, ahi1.y, ahi1.z, ahi1.w}};
-      const float bh[2][4] = {{bhi0.x, bhi0.y, bhi0.z, bhi0.w}, {bhi1.x, bhi1.y, bhi1.z, bhi1.w}};
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ah[i][s], bh[j][s], acc[i][j], 0, 0, 0);
-      if (more) {
+      frag(cur, 1, fhi_a, fhi_b);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_half(flo_a, flo_b);
+      __builtin_amdgcn_sched_barrier(0);
+      if (kb + 1 < nk) {
         store4(As(cur ^ 1), t, ra0);
         store4(As(cur ^ 1), t + 256, ra1);
         store4(Bs(cur ^ 1), t, rb0);
         store4(Bs(cur ^ 1), t + 256, rb1);
       }
-      __syncthreads();
+      __syncthreads();   // block kb + 1 stored; every wave's reads of buffer cur done
+      if (kb + 2 < nk) {
+        ra0 = load_a((kb + 2) * BK, t);
+        ra1 = load_a((kb + 2) * BK, t + 256);
+        rb0 = ld.load1(l0, (kb + 2) * BK, t);
+        rb1 = ld.load1(l0, (kb + 2) * BK, t + 256);
+      }
+      if (kb + 1 < nk) frag(cur ^ 1, 0, flo_a, flo_b);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_half(fhi_a, fhi_b);
+      __builtin_amdgcn_sched_barrier(0);
     }
-
     tile_epilogue(g, acc, smem, smin, smax, r0, l0, ld.L);
   }
   __syncthreads();

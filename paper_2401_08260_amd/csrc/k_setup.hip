@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void slice_setup_kernel(SetupArgs a) {
   // Tapered-coefficient recipe (Laplacian smooth part, Matern): samples v_j of the
   // function times the taper on u_j = -1/2 + j/L, then c_k = (1/L) sum_j v_j cos(2 pi k u_j).
   __shared__ SeriesTab tab;
-  __shared__ double part[512];
+  __shared__ double part[2048];
   const bool lap = (a.kernel == KSUM_LAPLACIAN);
   for (int i = threadIdx.x; i < kSeriesTab; i += blockDim.x) {
     tab.r0[i] = lap ? lap_r0(2 * i, a.d) : mat_r0(i, a.d);
@@ -199,8 +199,9 @@ __global__ __launch_bounds__(256) void slice_setup_kernel(SetupArgs a) {
   }
   __syncthreads();
   // DFT: c_k = (1/L) sum_j v_j cos(2 pi k u_j) = (-1)^k (1/L) sum_j v_j cos(2 pi k j / L), the
-  // cosine by rotation from the exact table value every 64 steps.  With few coefficients
-  // the j range of each k is split over S threads and the partial sums added in order.
+  // cosine by rotation from the exact table value every 64 steps.  The j range of each k
+  // is split over S threads (up to 8, K1 S <= 2048), so that every thread runs short,
+  // independent rotation chains; the partial sums are added in order.
   const int K1 = a.K + 1;
   const int qL = L / 4;                    // sin(x) = cos(x - pi/2)
   auto dft_range = [&](int k, int j0, int j1) {
@@ -227,7 +228,7 @@ __global__ __launch_bounds__(256) void slice_setup_kernel(SetupArgs a) {
     if (a.nfft) c *= (double)a.deconv[k];
     coef[k] = (float)c;
   };
-  const int S = (K1 >= (int)blockDim.x) ? 1 : min(8, (int)blockDim.x / K1);   // K1 * S <= 512
+  const int S = max(1, min(8, 2048 / K1));
   if (S == 1) {
     for (int k = threadIdx.x; k < K1; k += blockDim.x) finish(k, dft_range(k, 0, L));
     return;
