@@ -213,14 +213,15 @@ __global__ __launch_bounds__(1024) void sort_scan_kernel(SortArgs a) {
 // stay in registers until they are placed, and the tile counters alternate
 // between two arrays, so a tile takes four barriers plus the one of its scan.
 // ---------------------------------------------------------------------------
-constexpr int kScatTile = 4096;
-constexpr int kScatPer = kScatTile / 512;
+constexpr int kScatTile = 8192;
+constexpr int kScatThreads = 1024;
+constexpr int kScatPer = kScatTile / kScatThreads;
 
-__global__ __launch_bounds__(512) void sort_scatter_kernel(SortArgs a) {
+__global__ __launch_bounds__(kScatThreads) void sort_scatter_kernel(SortArgs a) {
   __shared__ unsigned long long tk[kScatTile];
   __shared__ uint16_t tb[kScatTile];
   __shared__ uint32_t cursor[2048], tcnt[2][2048], tstart[2048];
-  __shared__ uint32_t red[8];
+  __shared__ uint32_t red[kScatThreads / 64];
   const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * kSortChunks);
   if (work < 0) return;
   const int p = (int)(work / kSortChunks), c = (int)(work % kSortChunks);
@@ -235,11 +236,11 @@ __global__ __launch_bounds__(512) void sort_scatter_kernel(SortArgs a) {
   const int64_t l0 = c * chunk, l1 = min(a.L, l0 + chunk);
   const float *Zp = a.Z + (int64_t)p * a.L;
   unsigned long long *kp = a.keys + (int64_t)p * a.L;
-  const int per = (a.nb + 511) / 512;    // buckets per thread in the scan (<= 4)
+  const int per = (a.nb + kScatThreads - 1) / kScatThreads;    // buckets per thread in the scan
   float zn[kScatPer];
 #pragma unroll
   for (int q = 0; q < kScatPer; ++q) {
-    const int64_t l = l0 + threadIdx.x + q * 512;
+    const int64_t l = l0 + threadIdx.x + q * kScatThreads;
     zn[q] = (l < l1) ? Zp[l] : 0.f;
   }
   __syncthreads();
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(512) void sort_scatter_kernel(SortArgs a) {
     if (t0 + kScatTile < l1) {
 #pragma unroll
       for (int q = 0; q < kScatPer; ++q) {
-        const int64_t l = t0 + kScatTile + threadIdx.x + q * 512;
+        const int64_t l = t0 + kScatTile + threadIdx.x + q * kScatThreads;
         zn[q] = (l < l1) ? Zp[l] : 0.f;
       }
     }
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(512) void sort_scatter_kernel(SortArgs a) {
     unsigned long long kv[kScatPer];
 #pragma unroll
     for (int q = 0; q < kScatPer; ++q) {
-      const int i = threadIdx.x + q * 512;
+      const int i = threadIdx.x + q * kScatThreads;
       bk[q] = 0;
       rk[q] = 0;
       kv[q] = 0;
@@ -281,7 +282,7 @@ __global__ __launch_bounds__(512) void sort_scatter_kernel(SortArgs a) {
       if (b < a.nb) loc += cntb[b];
     }
     uint32_t tot;
-    uint32_t ex = block_excl_sum<8>(loc, red, &tot);
+    uint32_t ex = block_excl_sum<kScatThreads / 64>(loc, red, &tot);
     for (int q = 0; q < per; ++q) {
       const int b = threadIdx.x * per + q;
       if (b < a.nb) {
@@ -293,7 +294,7 @@ __global__ __launch_bounds__(512) void sort_scatter_kernel(SortArgs a) {
     // place the tile in bucket order in LDS (entries of one bucket stay in tile order)
 #pragma unroll
     for (int q = 0; q < kScatPer; ++q) {
-      const int i = threadIdx.x + q * 512;
+      const int i = threadIdx.x + q * kScatThreads;
       if (i < tn) {
         const uint32_t pos = tstart[bk[q]] + rk[q];
         tk[pos] = kv[q];
@@ -1135,7 +1136,7 @@ hipError_t launch_sort_path(const ExecArgs &a) {
   mark(a, ST_SORT_SCAN);
   sort_scan_kernel<<<a.nsl, 1024, 0, a.stream>>>(s);
   mark(a, ST_SORT_SCATTER);
-  sort_scatter_kernel<<<g1, 512, 0, a.stream>>>(s);
+  sort_scatter_kernel<<<g1, kScatThreads, 0, a.stream>>>(s);
   const int64_t items = (int64_t)a.nsl * lay.sort_groups;
   const unsigned g4 = (unsigned)std::min<int64_t>(xcd_grid(items), 256 * 2);
   mark(a, ST_SORT_GROUP);
