@@ -103,6 +103,25 @@ def test_negdist_parity_and_permutation(N, M, d, P):
     assert sliced.rel_l2(r["t"].astype(np.float64), ts) <= TOL
 
 
+def test_negdist_max_buckets_large_union():
+    """A union of 1.2 million points takes the largest bucket count of the sort path (2048):
+    two buckets per thread in the scatter's tile scan, many groups per slice.  Permutations
+    bit-exact, per-slice sums and the average against the oracle."""
+    rng = np.random.default_rng(2048)
+    N, M, d, P = 600000, 600000, 8, 4
+    x = rng.standard_normal((N, d)).astype(np.float32)
+    y = rng.standard_normal((M, d)).astype(np.float32)
+    w = rng.random(N).astype(np.float32)
+    note(f"negdist max buckets N={N} M={M} d={d} P={P}")
+    r = run_gpu("negdist", x, y, w, P, seed=3, probe=True)
+    _check_perm(r["z"], r["perm"])
+    ref, ts = oracle_s("negdist", x, y, w, r["xi"], slices=True)
+    err = sliced.rel_l2(r["s"], ref)
+    note(f"  rel err {err:.3e}")
+    assert err <= TOL
+    assert sliced.rel_l2(r["t"].astype(np.float64), ts) <= TOL
+
+
 def test_negdist_signed_weights_and_ties():
     """Integer-valued coordinates give many equal projections (ties inside and across x, y)."""
     rng = np.random.default_rng(3)
