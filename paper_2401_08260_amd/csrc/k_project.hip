@@ -59,7 +59,7 @@ __device__ __forceinline__ void tile_epilogue(const GemmCtl &g, const f32x16 (&a
         if (row < g.nsl) {
           float *dst = g.Z + (int64_t)row * g.ldz + l;
           if (g.z_vec4 && l + 3 < L) {
-            *reinterpret_cast<float4 *>(dst) = v;
+            store_z4(dst, v);
           } else {
             if (l + 0 < L) dst[0] = v.x;
             if (l + 1 < L) dst[1] = v.y;

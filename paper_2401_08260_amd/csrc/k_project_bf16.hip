@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256, 2) void proj_gemm_bf16x3_kernel(GemmCtl g, Poi
           if (row < g.nsl) {
             float *dst = g.Z + (int64_t)row * g.ldz + l;
             if (g.z_vec4 && l + 3 < ld.L) {
-              *reinterpret_cast<float4 *>(dst) = v;
+              store_z4(dst, v);
             } else {
               if (l + 0 < ld.L) dst[0] = v.x;
               if (l + 1 < ld.L) dst[1] = v.y;

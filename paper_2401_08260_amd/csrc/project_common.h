@@ -48,6 +48,15 @@ struct PointLoader {
   }
 };
 
+// 16-byte store of four projections into Z with the non-temporal hint: Z is far
+// larger than the caches and is read back by the next stage only after the whole
+// GEMM, so keeping it out of the caches loses nothing
+__device__ __forceinline__ void store_z4(float *dst, float4 v) {
+  typedef float nt4 __attribute__((ext_vector_type(4)));
+  const nt4 nv = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(nv, reinterpret_cast<nt4 *>(dst));
+}
+
 struct GemmCtl {
   const float *dirs;
   int d_pad, p0, nsl;
