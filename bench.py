@@ -71,11 +71,15 @@ def kernel_work(stage, wl, P):
       nfft_spread   4 B projection + 4 B weight per source
       nfft_interp   4 B projection read + 4 B t write per target
       accumulate    4 B t per target-slice read
+      backproject   2 P flops per output coordinate     -> 2 R P d flops per launch, R = M (grad_y)
+                    or N (grad_x); counted as (N + M) P d, the mean of the two launches (MFMA FP32)
     """
     N, M, d = wl.N, wl.M, wl.d
     L = N + M
     if stage == "project":
         return "mfma", 2.0 * L * d * P / 1e12, "TFLOP/s", PEAK_FP32_MFMA_TFLOPS
+    if stage == "backproject":
+        return "mfma", 1.0 * L * d * P / 1e12, "TFLOP/s", PEAK_FP32_MFMA_TFLOPS
     gb = {
         "sort_group": (8.0 * L + 4.0 * N + 4.0 * M) * P,
         "sort_hist": (4.0 * L + 4.0 * N) * P,
@@ -438,6 +442,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-BF16 (mixed) leg")
     ap.add_argument("--no-gate", action="store_true", help="skip the run at the slice count of the error gate")
+    ap.add_argument("--backward", action="store_true",
+                    help="also time one gradient step (grad_x, grad_y, grad_w for an upstream grad_s)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device (reference for the HBM traffic counters)")
     args = ap.parse_args()
@@ -567,6 +573,39 @@ def main():
         log(f"[bench] mixed (split-BF16 projection): {ms_m:.3f} ms/step, {mixed['value']:.4e} {UNIT}, "
             f"x{mixed['speedup_vs_fp32']:.2f} vs FP32")
 
+    # timed region 4 (--backward): the gradients of an MMD gradient-flow step, grad_x, grad_y
+    # and grad_w of s for a seeded upstream grad_s, on the same inputs and plan
+    backward = None
+    if args.backward:
+        gs = torch.from_numpy(np.random.default_rng(7).standard_normal(wl.M).astype(np.float32)).to(dev)
+        for _ in range(args.warmup):
+            plan.backward(xt, yt, wt, gs)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            plan.backward(xt, yt, wt, gs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_b = float(e0.elapsed_time(e1)) / args.steps
+        ks.ksum_set_timing(plan.handle, True)
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            plan.backward(xt, yt, wt, gs)
+        torch.cuda.synchronize()
+        st_b = ks.ksum_stage_times(plan.handle)
+        ks.ksum_set_timing(plan.handle, False)
+        share_b = {k: v[0] / args.steps for k, v in st_b.items() if v[1] > 0}
+        backward = {"what": "grad_x, grad_y and grad_w of s for an upstream grad_s",
+                    "ms_per_step": ms_b, "stage_ms_per_step": share_b}
+        if st_b.get("backproject", (0.0, 0))[1] > 0:
+            bms = st_b["backproject"][0] / st_b["backproject"][1]
+            b_bound, b_amt, b_unit, b_pk = kernel_work("backproject", wl, wl.P)
+            backward["backproject_roofline"] = {"bound": b_bound, "avg_launch_ms": bms,
+                                                "achieved": b_amt / (bms * 1e-3), "peak": b_pk, "unit": b_unit,
+                                                "frac": b_amt / (bms * 1e-3) / b_pk}
+        log(f"[bench] backward (grad_x, grad_y, grad_w): {ms_b:.3f} ms/step")
+
     result = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "p50_ms": float(np.percentile(per, 50)),
@@ -581,6 +620,8 @@ def main():
         "stage_roofline": stage_roofline,
         "mixed": mixed,
     }
+    if backward is not None:
+        result["backward"] = backward
 
     if not args.no_cpu_baseline:
         probe_t = torch.empty((wl.P, wl.M), dtype=torch.float32, device=dev)

@@ -53,7 +53,7 @@ struct SliceParams {
 enum StageId {
   ST_MISC = 0, ST_PROJECT, ST_SETUP, ST_NDFT_ADJOINT, ST_NDFT_FORWARD, ST_NFFT_SPREAD, ST_NFFT_GRID,
   ST_NFFT_INTERP, ST_SORT_HIST, ST_SORT_SCAN, ST_SORT_SCATTER, ST_SORT_GROUP, ST_ACCUMULATE,
-  ST_SORT_FALLBACK, ST_COUNT
+  ST_SORT_FALLBACK, ST_BACKPROJ, ST_COUNT
 };
 
 struct Timer {
@@ -170,11 +170,13 @@ template <typename T> inline T *wsp(const ExecArgs &a, size_t off) {
 
 // Records a timing event on the execution stream: the interval up to the next
 // mark is attributed to `stage` (stage < 0 closes the interval).
-inline void mark(const ExecArgs &a, int stage) {
-  Timer *t = a.plan->timer;
+inline void mark(const ksum_plan *plan, hipStream_t stream, int stage) {
+  Timer *t = plan->timer;
   if (!t || t->used >= (int)t->ev.size()) return;
-  if (hipEventRecord(t->ev[t->used], a.stream) == hipSuccess) t->ids[t->used++] = stage;
+  if (hipEventRecord(t->ev[t->used], stream) == hipSuccess) t->ids[t->used++] = stage;
 }
+
+inline void mark(const ExecArgs &a, int stage) { mark(a.plan, a.stream, stage); }
 
 hipError_t launch_weight_prep(const ExecArgs &a, const double *w64);
 hipError_t launch_projection(const ExecArgs &a);

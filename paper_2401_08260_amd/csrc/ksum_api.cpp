@@ -425,6 +425,23 @@ ksum_status ksum_workspace_size(const ksum_plan *plan, int64_t N, int64_t M, siz
 
 // One pass of the hot path over all slices, batch by batch, on the plan's device:
 // forward sums into s, or (deriv) the per-target derivative sums into dout[M][ldd].
+// Stages of one slice batch after the projection and the set-up: the 1-D sums and the
+// running average into s or, in derivative mode, the per-slice derivative sums (a.dout).
+static hipError_t post_projection(const ExecArgs &a, float *s) {
+  const ksum_plan *plan = a.plan;
+  hipError_t e = hipSuccess;
+  if (plan->use_fourier) e = (plan->method == KSUM_1D_NDFT) ? launch_ndft(a) : launch_nfft(a);
+  if (e == hipSuccess && plan->use_sort) e = launch_sort_path(a);
+  const bool first = a.p0 == 0, last = a.p0 + a.nsl >= plan->P;
+  const bool interp = plan->use_fourier && plan->method == KSUM_1D_NFFT;
+  if (e == hipSuccess) {
+    if (interp) e = launch_nfft_interp(a, s, first, last);
+    else if (a.deriv) e = launch_deriv_gather(a);
+    else e = launch_accumulate(a, s, first, last);
+  }
+  return e;
+}
+
 static hipError_t run_pipeline(ksum_plan *plan, const Layout &lay, const void *x, const void *y, const void *w,
                                bool f64, float *s, bool deriv, float *dout, int64_t ldd, char *ws,
                                hipStream_t stream, const ksum_probe *probe) {
@@ -453,16 +470,7 @@ static hipError_t run_pipeline(ksum_plan *plan, const Layout &lay, const void *x
       e = hipMemcpyAsync(probe->z + (int64_t)p0 * lay.L, a.ws + lay.off_z, (size_t)a.nsl * lay.L * sizeof(float),
                          hipMemcpyDeviceToDevice, a.stream);
     if (e == hipSuccess && probe && probe->bounds) e = launch_bounds_probe(a, probe->bounds);
-    if (e == hipSuccess && plan->use_fourier)
-      e = (plan->method == KSUM_1D_NDFT) ? launch_ndft(a) : launch_nfft(a);
-    if (e == hipSuccess && plan->use_sort) e = launch_sort_path(a);
-    const bool first = p0 == 0, last = p0 + a.nsl >= plan->P;
-    const bool interp = plan->use_fourier && plan->method == KSUM_1D_NFFT;
-    if (e == hipSuccess) {
-      if (interp) e = launch_nfft_interp(a, s, first, last);
-      else if (deriv) e = launch_deriv_gather(a);
-      else e = launch_accumulate(a, s, first, last);
-    }
+    if (e == hipSuccess) e = post_projection(a, s);
   }
   mark(a, -1);
   return e;
@@ -499,11 +507,20 @@ static ksum_status execute_impl(ksum_plan *plan, const void *x, int64_t N, const
 
 // Workspace of the backward pass: the larger of the two pipeline layouts (targets y
 // and targets x), then the derivative sums D [max(N, M)][Pk].
-static size_t backward_bytes(const ksum_plan &pl, int64_t N, int64_t M, size_t *d_off) {
-  const size_t a = make_layout(pl, N, M).total, b = make_layout(pl, M, N).total;
-  const size_t off = align_up(std::max(a, b), 256);
-  if (d_off) *d_off = off;
-  return off + (size_t)std::max(N, M) * pl.Pk * sizeof(float);
+// Backward workspace: the forward layout with sources x and targets y (for dL/dy), the
+// one with the roles exchanged (for dL/dw and dL/dx), and the derivative sums
+// D^y [M][Pk] and D^x [N][Pk].
+struct BackwardOffsets {
+  size_t lx, dy, dx, total;
+};
+
+static BackwardOffsets backward_offsets(const ksum_plan &pl, int64_t N, int64_t M) {
+  BackwardOffsets o;
+  o.lx = align_up(make_layout(pl, N, M).total, 256);
+  o.dy = align_up(o.lx + make_layout(pl, M, N).total, 256);
+  o.dx = align_up(o.dy + (size_t)M * pl.Pk * sizeof(float), 256);
+  o.total = o.dx + (size_t)N * pl.Pk * sizeof(float);
+  return o;
 }
 
 ksum_status ksum_execute(ksum_plan *plan, const float *x, int64_t N, const float *y, int64_t M, const float *w,
@@ -532,7 +549,7 @@ ksum_status ksum_backward_workspace_size(const ksum_plan *plan, int64_t N, int64
   if (!plan || !bytes) return fail(KSUM_EINVAL, "null argument");
   if (N < 1 || M < 1) return fail(KSUM_EINVAL, "N and M must be >= 1");
   if (N + M > 0x7fffffffLL) return fail(KSUM_EUNSUPPORTED, "N + M must be < 2^31");
-  *bytes = backward_bytes(*plan, N, M, nullptr);
+  *bytes = backward_offsets(*plan, N, M).total;
   return KSUM_OK;
 }
 
@@ -542,37 +559,101 @@ ksum_status ksum_backward(ksum_plan *plan, const float *x, int64_t N, const floa
   const ksum_status st = check_exec_args(plan, x, N, y, M, w, ws);
   if (st != KSUM_OK) return st;
   if (!grad_s) return fail(KSUM_EINVAL, "grad_s is NULL");
-  size_t d_off = 0;
-  if (ws_bytes < backward_bytes(*plan, N, M, &d_off)) return fail(KSUM_EWORKSPACE, "workspace too small");
+  const BackwardOffsets bo = backward_offsets(*plan, N, M);
+  if (ws_bytes < bo.total) return fail(KSUM_EWORKSPACE, "workspace too small");
+  if (!grad_x && !grad_y && !grad_w) return KSUM_OK;
   int prev = 0;
   (void)hipGetDevice(&prev);
   if (prev != plan->params.device && hipSetDevice(plan->params.device) != hipSuccess)
     return fail(KSUM_EDEVICE, "hipSetDevice failed");
   char *wsc = static_cast<char *>(ws);
   const hipStream_t sm = static_cast<hipStream_t>(stream);
-  float *D = reinterpret_cast<float *>(wsc + d_off);
   const int64_t ldd = plan->Pk;
   const double invP = 1.0 / (double)plan->P;
+  float *Dy = reinterpret_cast<float *>(wsc + bo.dy);
+  float *Dx = reinterpret_cast<float *>(wsc + bo.dx);
+  // The three sums share their projections.  dL/dy needs the sums with sources x and
+  // targets y, whose union is (y, x); dL/dw (the sum with sources y, weights grad_s, and
+  // targets x) and dL/dx (its derivative sums) share the union (x, y).  Both unions hold
+  // the same points, so per slice batch the GEMM runs once: the second layout's Z is the
+  // same matrix with its two column blocks exchanged, and its per-block min / max
+  // partials are the same (the set-up of each layout then derives identical slice
+  // parameters).  dL/dy_m = grad_s_m / P sum_p D^y[m][p] xi_p and
+  // dL/dx_n = w_n / P sum_p D^x[n][p] xi_p follow by back-projection.
+  const Layout ly = make_layout(*plan, N, M), lx = make_layout(*plan, M, N);
+  const bool need_y = grad_y != nullptr, need_x = grad_w != nullptr || grad_x != nullptr;
+  ExecArgs ay{}, ax{};
+  ay.plan = ax.plan = plan;
+  ay.stream = ax.stream = sm;
+  ay.lay = &ly;
+  ay.ws = wsc;
+  ay.x = x;
+  ay.y = y;
+  ay.w = w;
+  ay.deriv = true;
+  ay.dout = Dy;
+  ay.ldd = ldd;
+  ax.lay = &lx;
+  ax.ws = wsc + bo.lx;
+  ax.x = y;
+  ax.y = x;
+  ax.w = grad_s;
+  ax.ldd = ldd;
   hipError_t e = hipSuccess;
-  // dL/dw: the sum with sources y (weights grad_s) and targets x
-  if (grad_w) {
-    const Layout lw = make_layout(*plan, M, N);
-    e = run_pipeline(plan, lw, y, x, grad_s, false, grad_w, false, nullptr, 0, wsc, sm, nullptr);
+  if (need_y) {
+    mark(plan, sm, ST_MISC);
+    e = launch_fill_zero(Dy, M * ldd, sm);
+    if (e == hipSuccess) e = launch_weight_prep(ay, nullptr);
   }
-  // dL/dy_m = grad_s_m / P * sum_p D^y[m][p] xi_p
+  if (e == hipSuccess && need_x) {
+    mark(plan, sm, ST_MISC);
+    if (grad_x) e = launch_fill_zero(Dx, N * ldd, sm);
+    if (e == hipSuccess) e = launch_weight_prep(ax, nullptr);
+  }
+  for (int32_t p0 = 0; p0 < plan->P && e == hipSuccess; p0 += ly.B) {
+    ay.p0 = ax.p0 = p0;
+    ay.nsl = ax.nsl = std::min(ly.B, plan->P - p0);
+    e = launch_projection(need_y ? ay : ax);
+    if (e == hipSuccess) e = launch_slice_setup(need_y ? ay : ax);
+    if (e == hipSuccess && need_y && need_x) {
+      // Z of (x, y) from Z of (y, x): rows of L floats, the first M columns of each row
+      // become the last M, and the per-block bound partials carry over
+      mark(plan, sm, ST_MISC);
+      const size_t row = (size_t)ly.L * sizeof(float);
+      const char *zy = wsc + ly.off_z;
+      char *zx = ax.ws + lx.off_z;
+      e = hipMemcpy2DAsync(zx, row, zy + (size_t)M * sizeof(float), row, (size_t)N * sizeof(float), ay.nsl,
+                           hipMemcpyDeviceToDevice, sm);
+      if (e == hipSuccess)
+        e = hipMemcpy2DAsync(zx + (size_t)N * sizeof(float), row, zy, row, (size_t)M * sizeof(float), ay.nsl,
+                             hipMemcpyDeviceToDevice, sm);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(ax.ws + lx.off_bounds_part, wsc + ly.off_bounds_part,
+                           (size_t)projection_blocks(*plan, ly.L, ay.nsl) * ay.nsl * 2 * sizeof(uint32_t),
+                           hipMemcpyDeviceToDevice, sm);
+      if (e == hipSuccess) e = launch_slice_setup(ax);
+    }
+    if (e == hipSuccess && need_y) e = post_projection(ay, nullptr);
+    if (e == hipSuccess && grad_w) {
+      ax.deriv = false;
+      ax.dout = nullptr;
+      e = post_projection(ax, grad_w);
+    }
+    if (e == hipSuccess && grad_x) {
+      ax.deriv = true;
+      ax.dout = Dx;
+      e = post_projection(ax, nullptr);
+    }
+  }
   if (e == hipSuccess && grad_y) {
-    const Layout ly = make_layout(*plan, N, M);
-    e = launch_fill_zero(D, M * ldd, sm);
-    if (e == hipSuccess) e = run_pipeline(plan, ly, x, y, w, false, nullptr, true, D, ldd, wsc, sm, nullptr);
-    if (e == hipSuccess) e = launch_backproject(*plan, D, ldd, M, grad_s, invP, grad_y, sm);
+    mark(plan, sm, ST_BACKPROJ);
+    e = launch_backproject(*plan, Dy, ldd, M, grad_s, invP, grad_y, sm);
   }
-  // dL/dx_n = w_n / P * sum_p D^x[n][p] xi_p, D^x with sources y (weights grad_s) and targets x
   if (e == hipSuccess && grad_x) {
-    const Layout lx = make_layout(*plan, M, N);
-    e = launch_fill_zero(D, N * ldd, sm);
-    if (e == hipSuccess) e = run_pipeline(plan, lx, y, x, grad_s, false, nullptr, true, D, ldd, wsc, sm, nullptr);
-    if (e == hipSuccess) e = launch_backproject(*plan, D, ldd, N, w, invP, grad_x, sm);
+    mark(plan, sm, ST_BACKPROJ);
+    e = launch_backproject(*plan, Dx, ldd, N, w, invP, grad_x, sm);
   }
+  mark(plan, sm, -1);
   if (prev != plan->params.device) (void)hipSetDevice(prev);
   if (e != hipSuccess) return fail(KSUM_EDEVICE, std::string("HIP launch failed: ") + hipGetErrorString(e));
   return KSUM_OK;
@@ -580,7 +661,8 @@ ksum_status ksum_backward(ksum_plan *plan, const float *x, int64_t N, const floa
 
 static const char *kStageNames[ST_COUNT] = {
     "misc", "project", "setup", "ndft_adjoint", "ndft_forward", "nfft_spread", "nfft_grid",
-    "nfft_interp", "sort_hist", "sort_scan", "sort_scatter", "sort_group", "accumulate", "sort_fallback"};
+    "nfft_interp", "sort_hist", "sort_scan", "sort_scatter", "sort_group", "accumulate", "sort_fallback",
+    "backproject"};
 
 int32_t ksum_stage_count(void) { return ST_COUNT; }
 

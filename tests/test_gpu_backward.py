@@ -154,6 +154,40 @@ def test_autograd_function_and_translation_invariance():
     assert tot <= 1e-5 * scale
 
 
+@pytest.mark.parametrize("kernel", ["negdist", "laplacian"])
+def test_backward_subsets_and_batches(kernel):
+    """Every subset of the gradients equals the full backward bitwise (the projections are
+    shared between the sums of the gradient, or computed directly when only grad_x and grad_w
+    are asked for), over three slice batches (32, 32, 6) with ragged N != M; the full set
+    also against the oracle gradient."""
+    torch = _torch()
+    import paper_2401_08260_amd as ks
+    rng = np.random.default_rng(33)
+    N, M, d, P = 2100, 1300, 24, 70
+    x = rng.random((N, d), dtype=np.float32)
+    y = rng.random((M, d), dtype=np.float32)
+    w = rng.random(N).astype(np.float32)
+    g = rng.standard_normal(M).astype(np.float32)
+    kw = {}
+    if kernel == "laplacian":
+        kw = dict(sigma=float(np.sqrt(d / 6.0)), method="nfft", n_coeff=256, T=0.125)
+    note(f"backward subsets {kernel} N={N} M={M} d={d} P={P}")
+    r = check(kernel, x, y, w, g, P, seed=4, ref_kw=kw, slice_batch=32, **kw)
+    plan = ks.Plan(d, P, kernel, seed=4, slice_batch=32, **kw)
+    dev = torch.device("cuda:0")
+    xt, yt, wt, gt = (torch.from_numpy(a).to(dev) for a in (x, y, w, g))
+    full = [t.cpu().numpy() for t in plan.backward(xt, yt, wt, gt)]
+    for need in [(True, False, False), (False, True, False), (False, False, True), (True, False, True),
+                 (False, True, True), (True, True, False)]:
+        part = plan.backward(xt, yt, wt, gt, need_x=need[0], need_y=need[1], need_w=need[2])
+        torch.cuda.synchronize()
+        for k in range(3):
+            assert (part[k] is None) == (not need[k])
+            if part[k] is not None:
+                assert np.array_equal(part[k].cpu().numpy(), full[k]), (need, k)
+    assert np.array_equal(full[0].astype(np.float64), r["gx"])
+
+
 def test_backward_split_bf16():
     note("backward split-bf16 negdist")
     rng = np.random.default_rng(21)
