@@ -34,6 +34,7 @@ struct BackArgs {
   const float *scale;    // [R]
   float factor;
   float *out;            // [R][d]
+  int out_vec4;          // rows of out are 16-byte aligned (d % 4 == 0, out 16-byte aligned)
 };
 
 // 4 consecutive values of row `row` at column k of a [rows][ld] matrix (zero outside)
@@ -70,6 +71,27 @@ __global__ __launch_bounds__(256) void backproject_kernel(BackArgs g) {
     *reinterpret_cast<float4 *>(S + (e >> 2) * LDA + (e & 3) * 4) = v;
   };
 
+  // fragments of one half of a lane's 8 contraction indices (its first or last 4) in buffer b
+  auto frag = [&](int b, int half, float4 (&fa)[2], float4 (&fb)[2]) {
+    const float *pa = As(b) + (wm * 64 + lr) * LDA + lh * 8 + half * 4;
+    const float *pb = Bs(b) + (wn * 64 + lr) * LDA + lh * 8 + half * 4;
+    fa[0] = *reinterpret_cast<const float4 *>(pa);
+    fa[1] = *reinterpret_cast<const float4 *>(pa + 32 * LDA);
+    fb[0] = *reinterpret_cast<const float4 *>(pb);
+    fb[1] = *reinterpret_cast<const float4 *>(pb + 32 * LDA);
+  };
+  auto mfma_half = [&](const float4 (&fa)[2], const float4 (&fb)[2]) {
+    const float av[2][4] = {{fa[0].x, fa[0].y, fa[0].z, fa[0].w}, {fa[1].x, fa[1].y, fa[1].z, fa[1].w}};
+    const float bv[2][4] = {{fb[0].x, fb[0].y, fb[0].z, fb[0].w}, {fb[1].x, fb[1].y, fb[1].z, fb[1].w}};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i][s], bv[j][s], acc[i][j], 0, 0, 0);
+  };
+
   float4 ra0 = ldA(0, t), ra1 = ldA(0, t + 256);
   float4 rb0 = ldB(0, t), rb1 = ldB(0, t + 256);
   st4(As(0), t, ra0);
@@ -77,40 +99,40 @@ __global__ __launch_bounds__(256) void backproject_kernel(BackArgs g) {
   st4(Bs(0), t, rb0);
   st4(Bs(0), t + 256, rb1);
   __syncthreads();
+  if (nk > 1) {
+    ra0 = ldA(BK, t);
+    ra1 = ldA(BK, t + 256);
+    rb0 = ldB(BK, t);
+    rb1 = ldB(BK, t + 256);
+  }
+  float4 flo_a[2], flo_b[2], fhi_a[2], fhi_b[2];
+  frag(0, 0, flo_a, flo_b);
+  // software pipeline over the K-blocks (as in the projection GEMM): the second half's
+  // fragments are read during the first half's MFMAs, and after the barrier the next
+  // block's first-half reads overlap the second half's MFMAs
   for (int kb = 0; kb < nk; ++kb) {
     const int cur = kb & 1;
-    const bool more = kb + 1 < nk;
-    if (more) {
-      ra0 = ldA((kb + 1) * BK, t);
-      ra1 = ldA((kb + 1) * BK, t + 256);
-      rb0 = ldB((kb + 1) * BK, t);
-      rb1 = ldB((kb + 1) * BK, t + 256);
-    }
-    const float *pa0 = As(cur) + (wm * 64 + lr) * LDA + lh * 8;
-    const float *pb0 = Bs(cur) + (wn * 64 + lr) * LDA + lh * 8;
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      const float4 a0 = *reinterpret_cast<const float4 *>(pa0 + half * 4);
-      const float4 a1 = *reinterpret_cast<const float4 *>(pa0 + 32 * LDA + half * 4);
-      const float4 b0 = *reinterpret_cast<const float4 *>(pb0 + half * 4);
-      const float4 b1 = *reinterpret_cast<const float4 *>(pb0 + 32 * LDA + half * 4);
-      const float av[2][4] = {{a0.x, a0.y, a0.z, a0.w}, {a1.x, a1.y, a1.z, a1.w}};
-      const float bv[2][4] = {{b0.x, b0.y, b0.z, b0.w}, {b1.x, b1.y, b1.z, b1.w}};
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i][s], bv[j][s], acc[i][j], 0, 0, 0);
-    }
-    if (more) {
+    frag(cur, 1, fhi_a, fhi_b);
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_half(flo_a, flo_b);
+    __builtin_amdgcn_sched_barrier(0);
+    if (kb + 1 < nk) {
       st4(As(cur ^ 1), t, ra0);
       st4(As(cur ^ 1), t + 256, ra1);
       st4(Bs(cur ^ 1), t, rb0);
       st4(Bs(cur ^ 1), t + 256, rb1);
     }
-    __syncthreads();
+    __syncthreads();   // block kb + 1 stored; every wave's reads of buffer cur done
+    if (kb + 2 < nk) {
+      ra0 = ldA((kb + 2) * BK, t);
+      ra1 = ldA((kb + 2) * BK, t + 256);
+      rb0 = ldB((kb + 2) * BK, t);
+      rb1 = ldB((kb + 2) * BK, t + 256);
+    }
+    if (kb + 1 < nk) frag(cur ^ 1, 0, flo_a, flo_b);
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_half(fhi_a, fhi_b);
+    __builtin_amdgcn_sched_barrier(0);
   }
 
   // epilogue in two halves of 64 rows through LDS: each thread writes 16 values of a row
@@ -136,9 +158,18 @@ __global__ __launch_bounds__(256) void backproject_kernel(BackArgs g) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int c = (t & 7) * 4 + 32 * k;
+          const float4 v = *reinterpret_cast<const float4 *>(smem + lrow * LDC + c);
+          if (g.out_vec4 && c0 + c + 3 < g.d) {
+            // 16-byte non-temporal store: the gradient is far larger than the caches
+            typedef float nt4 __attribute__((ext_vector_type(4)));
+            const nt4 nv = {sc * v.x, sc * v.y, sc * v.z, sc * v.w};
+            __builtin_nontemporal_store(nv, reinterpret_cast<nt4 *>(dst + c0 + c));
+          } else {
+            const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (c0 + c + u < g.d) dst[c0 + c + u] = sc * smem[lrow * LDC + c + u];
+            for (int u = 0; u < 4; ++u)
+              if (c0 + c + u < g.d) dst[c0 + c + u] = sc * vv[u];
+          }
         }
       }
     }
@@ -158,6 +189,7 @@ hipError_t launch_backproject(const ksum_plan &plan, const float *D, int64_t ldd
   g.scale = scale;
   g.factor = (float)factor;
   g.out = out;
+  g.out_vec4 = (plan.d % 4 == 0 && (uintptr_t)out % 16 == 0) ? 1 : 0;
   dim3 grid((unsigned)((R + TB - 1) / TB), (unsigned)((plan.d + TB - 1) / TB));
   backproject_kernel<<<grid, 256, 0, stream>>>(g);
   return hipGetLastError();
