@@ -160,6 +160,9 @@ struct ExecArgs {
   int32_t *perm_out;      // [P][L] or null
   float *t_out;           // [P][M] or null (probe)
   bool deriv;             // derivative sums instead of sums (backward)
+  bool reuse_front;       // the spread grid partials and the sort path's buckets (keys, bucket
+                          // prefixes, group descriptors) of this workspace are current for this
+                          // batch: only the stages after them run (sums that differ in mode only)
   float *dout;            // derivative mode: [M][ldd] per-target, per-slice derivative sums
   int64_t ldd;
 };

@@ -465,15 +465,17 @@ static void launch_nfft_m(const FourierArgs &f, const ExecArgs &a) {
   if (grid_lds > 65536)
     (void)hipFuncSetAttribute((const void *)nfft_grid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)grid_lds);
-  mark(a, ST_NFFT_SPREAD);
-  switch (f.share) {
-    case 1: launch_spread_sh<MW, DEG, 1>(f, a, gs); break;
-    case 2: launch_spread_sh<MW, DEG, 2>(f, a, gs); break;
-    case 4: launch_spread_sh<MW, DEG, 4>(f, a, gs); break;
-    case 8: launch_spread_sh<MW, DEG, 8>(f, a, gs); break;
-    case 16: launch_spread_sh<MW, DEG, 16>(f, a, gs); break;
-    case 32: launch_spread_sh<MW, DEG, 32>(f, a, gs); break;
-    default: launch_spread_sh<MW, DEG, 64>(f, a, gs); break;
+  if (!a.reuse_front) {   // the spread does not depend on the derivative mode
+    mark(a, ST_NFFT_SPREAD);
+    switch (f.share) {
+      case 1: launch_spread_sh<MW, DEG, 1>(f, a, gs); break;
+      case 2: launch_spread_sh<MW, DEG, 2>(f, a, gs); break;
+      case 4: launch_spread_sh<MW, DEG, 4>(f, a, gs); break;
+      case 8: launch_spread_sh<MW, DEG, 8>(f, a, gs); break;
+      case 16: launch_spread_sh<MW, DEG, 16>(f, a, gs); break;
+      case 32: launch_spread_sh<MW, DEG, 32>(f, a, gs); break;
+      default: launch_spread_sh<MW, DEG, 64>(f, a, gs); break;
+    }
   }
   mark(a, ST_NFFT_GRID);
   nfft_grid_kernel<<<a.nsl, 256, grid_lds, a.stream>>>(f);

@@ -56,7 +56,8 @@ struct SortArgs {
   float *t;             // [nsl][M]
   int32_t *perm;        // [nsl][L] (already offset to the batch) or null
   double cneg;          // c' (c_d, or alpha c_d for the Laplacian)
-  uint32_t *fail_count; // groups handed to the fallback kernel (zeroed by the scan kernel)
+  uint32_t *fail_count; // groups handed to the fallback kernel (zeroed by the scan kernel, or by the
+                        // host-side launch when the buckets are reused)
   uint32_t *fail_list;  // [nsl * G] work items
   int4 *desc;           // [nsl][G] (first bucket, first entry, end entry, 0) of each group
   int32_t deriv;        // 0: t = the sums; 1: t = their derivatives at the targets
@@ -1131,12 +1132,19 @@ hipError_t launch_sort_path(const ExecArgs &a) {
   s.cneg = pl.sort_const;
   s.deriv = a.deriv ? 1 : 0;
   const unsigned g1 = (unsigned)xcd_grid((int64_t)a.nsl * kSortChunks);
-  mark(a, ST_SORT_HIST);
-  sort_hist_kernel<<<g1, 512, 0, a.stream>>>(s);
-  mark(a, ST_SORT_SCAN);
-  sort_scan_kernel<<<a.nsl, 1024, 0, a.stream>>>(s);
-  mark(a, ST_SORT_SCATTER);
-  sort_scatter_kernel<<<g1, kScatThreads, 0, a.stream>>>(s);
+  if (!a.reuse_front) {   // histogram, scan and scatter do not depend on the derivative mode
+    mark(a, ST_SORT_HIST);
+    sort_hist_kernel<<<g1, 512, 0, a.stream>>>(s);
+    mark(a, ST_SORT_SCAN);
+    sort_scan_kernel<<<a.nsl, 1024, 0, a.stream>>>(s);
+    mark(a, ST_SORT_SCATTER);
+    sort_scatter_kernel<<<g1, kScatThreads, 0, a.stream>>>(s);
+  } else {
+    // the scan, which clears the fallback list, does not run: clear it here
+    mark(a, ST_MISC);
+    const hipError_t e = launch_fill_zero(reinterpret_cast<float *>(s.fail_count), 1, a.stream);
+    if (e != hipSuccess) return e;
+  }
   const int64_t items = (int64_t)a.nsl * lay.sort_groups;
   const unsigned g4 = (unsigned)std::min<int64_t>(xcd_grid(items), 256 * 2);
   mark(a, ST_SORT_GROUP);

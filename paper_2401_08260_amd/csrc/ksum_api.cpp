@@ -640,9 +640,13 @@ ksum_status ksum_backward(ksum_plan *plan, const float *x, int64_t N, const floa
       e = post_projection(ax, grad_w);
     }
     if (e == hipSuccess && grad_x) {
+      // same sources, weights and targets as the dL/dw sums just made: their spread grid
+      // partials and sort buckets are reused, only the mode-dependent stages run again
       ax.deriv = true;
       ax.dout = Dx;
+      ax.reuse_front = grad_w != nullptr;
       e = post_projection(ax, nullptr);
+      ax.reuse_front = false;
     }
   }
   if (e == hipSuccess && grad_y) {
