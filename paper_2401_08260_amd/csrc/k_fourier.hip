@@ -27,7 +27,7 @@ namespace ksum {
 // NDFT
 // ---------------------------------------------------------------------------
 constexpr int kNdftChunk = 4096;   // sources per adjoint block
-constexpr int kNdftKB = 32;        // coefficients per register block
+constexpr int kNdftKB = 8;         // coefficients per adjoint block (one k-group)
 
 struct FourierArgs {
   int32_t nsl, K, chunks;
@@ -49,16 +49,22 @@ struct FourierArgs {
   int32_t deriv;           // derivative sums (coefficients times 2 pi i k, result times tau)
 };
 
+// One block per (slice, chunk of sources, group of kNdftKB coefficients): the
+// coefficient groups run in parallel, so a small problem still fills the chip.
 __global__ __launch_bounds__(256) void ndft_adjoint_kernel(FourierArgs a) {
   __shared__ float2 red[4][kNdftKB];
-  const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * a.chunks);
+  const int ng = (a.K + kNdftKB) / kNdftKB;   // k-groups covering 0..K
+  const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * a.chunks * ng);
   if (work < 0) return;
-  const int p = (int)(work / a.chunks), c = (int)(work % a.chunks);
+  const int g = (int)(work % ng);
+  const int64_t pc = work / ng;
+  const int p = (int)(pc / a.chunks), c = (int)(pc % a.chunks);
   const SliceParams sp = a.params[p];
   const float *Zx = a.Z + (int64_t)p * a.L + a.M;
   const int64_t n0 = (int64_t)c * kNdftChunk, n1 = min(a.N, n0 + kNdftChunk);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int kb = 0; kb <= a.K; kb += kNdftKB) {
+  {
+    const int kb = g * kNdftKB;
     float re[kNdftKB], im[kNdftKB];
 #pragma unroll
     for (int q = 0; q < kNdftKB; ++q) re[q] = im[q] = 0.f;
@@ -157,8 +163,9 @@ hipError_t launch_ndft(const ExecArgs &a) {
   f.t = wsp<float>(a, lay.off_t1);
   f.deriv = a.deriv ? 1 : 0;
   mark(a, ST_NDFT_ADJOINT);
-  ndft_adjoint_kernel<<<(unsigned)xcd_grid((int64_t)a.nsl * f.chunks), 256, 0, a.stream>>>(f);
-  const int ychunk = 2048;
+  const int ng = (pl.K + kNdftKB) / kNdftKB;
+  ndft_adjoint_kernel<<<(unsigned)xcd_grid((int64_t)a.nsl * f.chunks * ng), 256, 0, a.stream>>>(f);
+  const int ychunk = 256;   // one target per thread: small problems still fill the chip
   const int nyc = (int)((lay.M + ychunk - 1) / ychunk);
   mark(a, ST_NDFT_FORWARD);
   ndft_forward_kernel<<<(unsigned)xcd_grid((int64_t)a.nsl * nyc), 256, (pl.K + 1) * sizeof(float2),
