@@ -207,6 +207,25 @@ def test_gauss_nfft_workload_reduced():
     assert err <= TOL
 
 
+@pytest.mark.parametrize("m,tol", [(2, 1e-3), (3, 1e-4), (4, TOL), (5, TOL), (7, TOL), (8, TOL)])
+def test_gauss_nfft_window_widths(m, tol):
+    """The NFFT with other Kaiser-Bessel half-widths m than the workloads' 6 (each m is its own
+    kernel instance).  The oracle sums the truncated Fourier series exactly, so the difference
+    is the window's aliasing error, which falls roughly like exp(-2 pi m sqrt(1 - 1/sigma)) for
+    oversampling sigma = 2 (about 1e-4 at m = 2, 1e-6 at m = 3), above the FP32 floor only for
+    m <= 3: the tolerance is 1e-5 from m = 4 on."""
+    wl = wlm.scaled(wlm.WORKLOADS["gauss_nfft"], N=6000, M=4000, P=4)
+    x, y, w = wlm.generate(wl)
+    sigma = wlm.median_heuristic(x, y)
+    note(f"gauss_nfft window m={m}")
+    r = run_gpu("gaussian", x, y, w, wl.P, seed=wl.dir_seed, sigma=sigma, n_coeff=wl.n_coeff, T=wl.T,
+                method="nfft", oversample=2, window_m=m)
+    ref = oracle_s("gaussian", x, y, w, r["xi"], sigma, "nfft", wl.n_coeff, wl.T)
+    err = sliced.rel_l2(r["s"], ref)
+    note(f"  rel err {err:.3e}")
+    assert err <= tol
+
+
 def test_laplace_workload_reduced():
     wl = wlm.scaled(wlm.WORKLOADS["laplace"], N=4000, M=3000, P=6)
     x, y, w = wlm.generate(wl)
