@@ -226,6 +226,24 @@ def test_gauss_nfft_window_widths(m, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("kernel,n_coeff,oversample", [("gaussian", 64, 2), ("gaussian", 256, 2),
+                                                      ("gaussian", 128, 4), ("laplacian", 512, 2)])
+def test_nfft_grid_sizes(kernel, n_coeff, oversample):
+    """Other coefficient counts and oversampling factors than the workloads': FFT lengths 128
+    to 1024 in LDS, and with them other window widths and lane sharing in the spread."""
+    base = "gauss_nfft" if kernel == "gaussian" else "laplace"
+    wl = wlm.scaled(wlm.WORKLOADS[base], N=5000, M=3500, P=4)
+    x, y, w = wlm.generate(wl)
+    sigma = wlm.median_heuristic(x, y)
+    note(f"{kernel} nfft n_coeff={n_coeff} oversample={oversample}")
+    r = run_gpu(kernel, x, y, w, wl.P, seed=wl.dir_seed, sigma=sigma, n_coeff=n_coeff, T=wl.T,
+                method="nfft", oversample=oversample, window_m=6)
+    ref = oracle_s(kernel, x, y, w, r["xi"], sigma, "nfft", n_coeff, wl.T)
+    err = sliced.rel_l2(r["s"], ref)
+    note(f"  rel err {err:.3e}")
+    assert err <= TOL
+
+
 def test_laplace_workload_reduced():
     wl = wlm.scaled(wlm.WORKLOADS["laplace"], N=4000, M=3000, P=6)
     x, y, w = wlm.generate(wl)
