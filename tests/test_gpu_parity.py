@@ -122,6 +122,24 @@ def test_negdist_max_buckets_large_union():
     assert sliced.rel_l2(r["t"].astype(np.float64), ts) <= TOL
 
 
+def test_negdist_more_slices_than_a_batch():
+    """P = 2100 slices with the default slice batch, which the library caps at 1024: three
+    batches (1024, 1024, 52) and the running average across them; ragged N, M."""
+    rng = np.random.default_rng(2100)
+    N, M, d, P = 700, 450, 12, 2100
+    x = rng.random((N, d), dtype=np.float32)
+    y = rng.random((M, d), dtype=np.float32)
+    w = rng.random(N).astype(np.float32)
+    note(f"negdist P={P} N={N} M={M} d={d}")
+    r = run_gpu("negdist", x, y, w, P, seed=21, probe=True)
+    _check_perm(r["z"][::97], r["perm"][::97])
+    ref, ts = oracle_s("negdist", x, y, w, r["xi"], slices=True)
+    err = sliced.rel_l2(r["s"], ref)
+    note(f"  rel err {err:.3e}")
+    assert err <= TOL
+    assert sliced.rel_l2(r["t"].astype(np.float64), ts) <= TOL
+
+
 def test_negdist_signed_weights_and_ties():
     """Integer-valued coordinates give many equal projections (ties inside and across x, y)."""
     rng = np.random.default_rng(3)
