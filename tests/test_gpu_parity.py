@@ -212,6 +212,25 @@ def test_gauss_ndft_ragged_fp32():
         assert sliced.rel_l2(r["s"], ref) <= TOL
 
 
+@pytest.mark.parametrize("n_coeff", [2, 16, 30])
+def test_gauss_ndft_coefficient_counts(n_coeff):
+    """The NDFT adjoint takes its coefficients in groups of 8, one block per group: K + 1 = 2
+    (one partial group), 9 (a full group and one) and 16 (two full groups), with two chunks of
+    sources and a partial target chunk."""
+    rng = np.random.default_rng(n_coeff)
+    N, M, d, P = 5000, 700, 10, 5
+    x = rng.standard_normal((N, d)).astype(np.float32)
+    y = rng.standard_normal((M, d)).astype(np.float32)
+    w = rng.random(N).astype(np.float32)
+    sigma = float(np.sqrt(2 * d))
+    note(f"gauss ndft n_coeff={n_coeff}")
+    r = run_gpu("gaussian", x, y, w, P, seed=8, sigma=sigma, n_coeff=n_coeff, T=0.045, method="ndft")
+    ref = oracle_s("gaussian", x, y, w, r["xi"], sigma, "ndft", n_coeff, 0.045)
+    err = sliced.rel_l2(r["s"], ref)
+    note(f"  rel err {err:.3e}")
+    assert err <= TOL
+
+
 def test_gauss_nfft_workload_reduced():
     wl = wlm.scaled(wlm.WORKLOADS["gauss_nfft"], N=20000, M=15000, P=6)
     x, y, w = wlm.generate(wl)
