@@ -450,7 +450,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        log("bench.py measures one GPU: this build has no multi-GPU path "
+        log("bench.py measures one GPU: the library has no multi-GPU path "
             "(slices would be sharded across GPUs with one all-reduce of s; see the design notes).")
         sys.exit(2)
 
