@@ -860,13 +860,16 @@ struct FastShared {
   uint32_t flag;
 };
 
+// The keys are read once, so they are loaded non-temporally: they then do not push
+// out of L2 the lines of t that the slice's other groups have yet to fill in
+// (t is written by target index, a few values per line per group).
 __device__ __forceinline__ void load_group_keys(const SortArgs &a, const GroupDesc &d,
                                                 unsigned long long (&kr)[kFPer]) {
   const unsigned long long *seg = a.keys + (int64_t)d.p * a.L + d.e_lo;
 #pragma unroll
   for (int q = 0; q < kFPer; ++q) {
     const int i = threadIdx.x + kFThreads * q;
-    kr[q] = (d.n <= kSortCap && i < d.n) ? seg[i] : ~0ull;
+    kr[q] = (d.n <= kSortCap && i < d.n) ? __builtin_nontemporal_load(seg + i) : ~0ull;
   }
 }
 
