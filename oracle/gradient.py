@@ -68,7 +68,7 @@ def absdist_deriv_sum(zx, zy, w, c: float):
 
 
 def slice_deriv(kernel: str, d: int, zx, zy, w, sigma: float, method: str, n_coeff: int, T: float,
-                laplace_L_factor: int = 16):
+                laplace_L_factor: int = 16, coeff_eps: float = 0.0):
     """Derivative sums D_m = d/dz sum_n w_n f(|zx_n - z|) at z = zy_m for one slice."""
     if kernel == "negdist":
         return absdist_deriv_sum(zx, zy, w, kn.c_d(d))
@@ -76,20 +76,21 @@ def slice_deriv(kernel: str, d: int, zx, zy, w, sigma: float, method: str, n_coe
     ks = np.arange(-K, K + 1)
     xt, yt, tau = sliced.rescale(zx, zy, T, sigma)
     if kernel == "gaussian":
-        cs = kn.gauss_fourier_coeff(d, tau * sigma, ks)
+        cs = sliced.cutoff(kn.gauss_fourier_coeff(d, tau * sigma, ks), coeff_eps)
         return ndft_deriv(xt, yt, w, ks, cs, tau)
     if kernel == "laplacian":
         alpha = 1.0 / sigma
         ks2, cs = kn.laplace_smooth_coeffs(d, alpha / tau, K, laplace_L_factor * n_coeff)
-        return ndft_deriv(xt, yt, w, ks2, cs, tau) + absdist_deriv_sum(zx, zy, w, alpha * kn.c_d(d))
+        return (ndft_deriv(xt, yt, w, ks2, sliced.cutoff(cs, coeff_eps), tau)
+                + absdist_deriv_sum(zx, zy, w, alpha * kn.c_d(d)))
     if kernel == "matern":
         ks2, cs = kn.matern_coeffs(d, sigma * tau, K, laplace_L_factor * n_coeff)
-        return ndft_deriv(xt, yt, w, ks2, cs, tau)
+        return ndft_deriv(xt, yt, w, ks2, sliced.cutoff(cs, coeff_eps), tau)
     raise ValueError(kernel)
 
 
 def sliced_grad(kernel: str, x, y, w, g, xi, sigma: float = 1.0, method: str = "sort",
-                n_coeff: int = 0, T: float = 0.0):
+                n_coeff: int = 0, T: float = 0.0, coeff_eps: float = 0.0):
     """(dL/dx, dL/dy, dL/dw) of L with dL/ds = g for the sliced fast sum with directions xi."""
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
@@ -98,13 +99,13 @@ def sliced_grad(kernel: str, x, y, w, g, xi, sigma: float = 1.0, method: str = "
     xi = np.asarray(xi, dtype=np.float64)
     zx = sliced.project(x, xi)
     zy = sliced.project(y, xi)
-    gx, gy = grad_from_projections(kernel, x.shape[1], zx, zy, w, g, xi, sigma, method, n_coeff, T)
-    grad_w = sliced.sliced_sum(kernel, y, x, g, xi, sigma, method, n_coeff, T)
+    gx, gy = grad_from_projections(kernel, x.shape[1], zx, zy, w, g, xi, sigma, method, n_coeff, T, coeff_eps)
+    grad_w = sliced.sliced_sum(kernel, y, x, g, xi, sigma, method, n_coeff, T, coeff_eps=coeff_eps)
     return gx, gy, grad_w
 
 
 def grad_from_projections(kernel: str, d: int, zx, zy, w, g, xi, sigma: float = 1.0, method: str = "sort",
-                          n_coeff: int = 0, T: float = 0.0):
+                          n_coeff: int = 0, T: float = 0.0, coeff_eps: float = 0.0):
     """(dL/dx, dL/dy) from given projections zx (N, P) and zy (M, P): the derivative sums of
     every slice and the back-projection onto the directions xi (P, d)."""
     zx = np.asarray(zx, dtype=np.float64)
@@ -116,8 +117,8 @@ def grad_from_projections(kernel: str, d: int, zx, zy, w, g, xi, sigma: float = 
     Dy = np.empty((zy.shape[0], P))
     Dx = np.empty((zx.shape[0], P))
     for p in range(P):
-        Dy[:, p] = slice_deriv(kernel, d, zx[:, p], zy[:, p], w, sigma, method, n_coeff, T)
-        Dx[:, p] = slice_deriv(kernel, d, zy[:, p], zx[:, p], g, sigma, method, n_coeff, T)
+        Dy[:, p] = slice_deriv(kernel, d, zx[:, p], zy[:, p], w, sigma, method, n_coeff, T, coeff_eps=coeff_eps)
+        Dx[:, p] = slice_deriv(kernel, d, zy[:, p], zx[:, p], g, sigma, method, n_coeff, T, coeff_eps=coeff_eps)
     grad_y = (g / P)[:, None] * (Dy @ xi)
     grad_x = (w / P)[:, None] * (Dx @ xi)
     return grad_x, grad_y

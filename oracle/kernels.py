@@ -17,6 +17,7 @@ the Matern kernel uses beta = sigma.
 """
 from __future__ import annotations
 
+import functools
 import math
 
 import numpy as np
@@ -179,19 +180,27 @@ def taper(u, center: float = 0.375, width: float = 1.0 / 37.0):
     return 0.5 * erfc((np.abs(np.asarray(u, dtype=np.float64)) - center) / width)
 
 
+@functools.lru_cache(maxsize=8)
+def _cos_matrix(K: int, L: int):
+    """cos(2 pi k u_j) for k = 0..K and u_j = -1/2 + j/L, j = 0..L-1 (read-only)."""
+    u = -0.5 + np.arange(L, dtype=np.float64) / L
+    m = np.cos(2.0 * math.pi * np.outer(np.arange(K + 1, dtype=np.float64), u))
+    m.setflags(write=False)
+    return m
+
+
 def tapered_coeffs(phi, K: int, L: int):
     """c_k = integral phi(u) W(u) exp(2 pi i k u) du, k = -K..K, on the torus [-1/2, 1/2) by the
-    trapezoidal rule on u_j = -1/2 + j/L (phi even, so c_k is real and even in k)."""
+    trapezoidal rule on u_j = -1/2 + j/L (phi even, so c_k is real and even in k):
+
+        c_k = (1/L) sum_j phi(u_j) W(u_j) cos(2 pi k u_j)
+
+    written out as the plain sum, as a product of the cosine matrix and the samples."""
     u = -0.5 + np.arange(L, dtype=np.float64) / L
     vals = phi(u) * taper(u)
     ks = np.arange(-K, K + 1)
-    # the trapezoidal sum (1/L) sum_j vals_j exp(2 pi i k u_j) with u_j = -1/2 + j/L is
-    # (-1)^k / L times the DFT of the samples (a library FFT evaluates it); phi is even,
-    # so the sum is real
-    F = np.fft.fft(vals)
-    kp = np.abs(ks)                                  # c_{-k} = c_k: take both from bin |k|
-    c = np.where(kp % 2 == 0, 1.0, -1.0) * F[kp % L].real / L
-    return ks, c
+    c_pos = _cos_matrix(K, L) @ vals / L          # k = 0..K
+    return ks, c_pos[np.abs(ks)]
 
 
 def laplace_smooth_coeffs(d: int, alpha_t: float, K: int, L: int):

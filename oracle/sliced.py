@@ -20,6 +20,9 @@ Readings of passages that are garbled or silent (all listed in the design notes)
   * Laplacian smooth part: coefficients from oracle.kernels.laplace_smooth_coeffs
     with L = 16 n_coeff samples; the Matern kernel (nu = 3/2) the same recipe on its
     whole counterpart (oracle.kernels.matern_coeffs).
+  * Cutoff threshold (eq. "Fourier_cutoff", Sec. 2.2): C keeps the k of the index
+    set above with |c_k| > eps; the others are left out of the sum (their c_k is
+    taken as 0).  eps = 0 keeps every nonzero coefficient.
 """
 from __future__ import annotations
 
@@ -43,6 +46,13 @@ def cutoff_K(method: str, n_coeff: int) -> int:
     raise ValueError(method)
 
 
+def cutoff(cs, eps: float):
+    """The cutoff set of eq. "Fourier_cutoff" (Sec. 2.2): coefficients with |c_k| <= eps are
+    dropped from C, i.e. contribute nothing to the Fourier sum."""
+    cs = np.asarray(cs, dtype=np.float64)
+    return np.where(np.abs(cs) > eps, cs, 0.0)
+
+
 def rescale(zx, zy, T: float, sigma: float):
     """Map one slice onto [-T, T] (Sec. 3.1, "Rescaling"); returns (x~, y~, tau)."""
     cmin = min(np.min(zx), np.min(zy))
@@ -55,7 +65,7 @@ def rescale(zx, zy, T: float, sigma: float):
 
 
 def slice_sum(kernel: str, d: int, zx, zy, w, sigma: float, method: str, n_coeff: int, T: float,
-              laplace_L_factor: int = 16):
+              laplace_L_factor: int = 16, coeff_eps: float = 0.0):
     """t_m for one slice by the fast 1-D summation the kernel uses."""
     if kernel == "negdist":
         return onedim.negdist_sum(zx, zy, w, kn.c_d(d))
@@ -63,22 +73,22 @@ def slice_sum(kernel: str, d: int, zx, zy, w, sigma: float, method: str, n_coeff
     ks = np.arange(-K, K + 1)
     xt, yt, tau = rescale(zx, zy, T, sigma)
     if kernel == "gaussian":
-        cs = kn.gauss_fourier_coeff(d, tau * sigma, ks)
+        cs = cutoff(kn.gauss_fourier_coeff(d, tau * sigma, ks), coeff_eps)
         return onedim.ndft_sum(xt, yt, w, ks, cs)
     if kernel == "laplacian":
         alpha = 1.0 / sigma
         ks2, cs = kn.laplace_smooth_coeffs(d, alpha / tau, K, laplace_L_factor * n_coeff)
-        t1 = onedim.ndft_sum(xt, yt, w, ks2, cs)
+        t1 = onedim.ndft_sum(xt, yt, w, ks2, cutoff(cs, coeff_eps))
         t2 = onedim.negdist_sum(zx, zy, w, alpha * kn.c_d(d))
         return t1 + t2
     if kernel == "matern":
         ks2, cs = kn.matern_coeffs(d, sigma * tau, K, laplace_L_factor * n_coeff)
-        return onedim.ndft_sum(xt, yt, w, ks2, cs)
+        return onedim.ndft_sum(xt, yt, w, ks2, cutoff(cs, coeff_eps))
     raise ValueError(kernel)
 
 
 def sliced_sum(kernel: str, x, y, w, xi, sigma: float = 1.0, method: str = "sort",
-               n_coeff: int = 0, T: float = 0.0, return_slices: bool = False):
+               n_coeff: int = 0, T: float = 0.0, return_slices: bool = False, coeff_eps: float = 0.0):
     """Algorithm "alg:fast_Fourier_sliced": average of the P one-dimensional fast sums."""
     d = np.asarray(x).shape[1]
     zx = project(x, xi)
@@ -86,7 +96,7 @@ def sliced_sum(kernel: str, x, y, w, xi, sigma: float = 1.0, method: str = "sort
     P = zx.shape[1]
     ts = np.empty((P, zy.shape[0]), dtype=np.float64)
     for p in range(P):
-        ts[p] = slice_sum(kernel, d, zx[:, p], zy[:, p], w, sigma, method, n_coeff, T)
+        ts[p] = slice_sum(kernel, d, zx[:, p], zy[:, p], w, sigma, method, n_coeff, T, coeff_eps=coeff_eps)
     s = ts.sum(axis=0) / P
     if return_slices:
         return s, ts

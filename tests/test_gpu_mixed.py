@@ -7,18 +7,23 @@ about u^2 |a b|, so a product is within 3 u^2 |a b| (plus the FP32 rounding of
 the inputs and of the accumulation).  Everything after the projection is the
 FP32 / FP64 arithmetic of the FP32 path, so the end results differ from the FP32
 path only through the projection; their error against the oracle is printed and
-gated at MIXED_TOL.
+gated at MIXED_TOL, normwise and per element (max |error| / max |result|).
+
+MIXED_TOL: a split-BF16 projection is within about 3 2^-16 sum_i |u_i xi_i| of the exact
+one where the FP32 projection is within about d 2^-24 sum_i |u_i xi_i|, i.e. 10 to 100 times
+less accurate on these workloads, whose FP32 end results are 1e-8 .. 2e-6 from the oracle;
+the split-BF16 end results measure 2.4e-7 .. 4.1e-6.  The gate, 2e-5, is five times the
+largest of them and five times tighter than the 1e-4 that was used before.
 """
 import numpy as np
 import pytest
 
 import workloads as wlm
-from oracle import sliced
-from test_gpu_parity import _check_perm, note, oracle_s, run_gpu
+from test_gpu_parity import _check_perm, assert_parity, note, oracle_s, run_gpu
 
 pytestmark = pytest.mark.gpu
 
-MIXED_TOL = 1e-4
+MIXED_TOL = 2e-5
 
 
 @pytest.mark.parametrize("N,M,d,P,f64", [(300, 200, 784, 16, False), (1000, 77, 50, 130, False),
@@ -55,9 +60,7 @@ def test_split_bf16_negdist_parity_and_permutation():
     r = run_gpu("negdist", x, y, w, P, seed=1, probe=True, precision="split_bf16")
     _check_perm(r["z"], r["perm"])
     ref = oracle_s("negdist", x, y, w, r["xi"])
-    err = sliced.rel_l2(r["s"], ref)
-    note(f"  rel err vs oracle {err:.3e}")
-    assert err <= MIXED_TOL
+    assert_parity(r["s"], ref, MIXED_TOL)
 
 
 def test_split_bf16_negdist_workload_full_size():
@@ -66,9 +69,7 @@ def test_split_bf16_negdist_workload_full_size():
     note("split-bf16 negdist full size")
     r = run_gpu("negdist", x, y, w, wl.P, seed=wl.dir_seed, precision="split_bf16")
     ref = oracle_s("negdist", x, y, w, r["xi"])
-    err = sliced.rel_l2(r["s"], ref)
-    note(f"  rel err vs oracle {err:.3e}")
-    assert err <= MIXED_TOL
+    assert_parity(r["s"], ref, MIXED_TOL)
 
 
 def test_split_bf16_gauss_ndft_workload_f64_input():
@@ -79,9 +80,7 @@ def test_split_bf16_gauss_ndft_workload_f64_input():
     r = run_gpu("gaussian", x, y, w, wl.P, seed=wl.dir_seed, sigma=sigma, n_coeff=wl.n_coeff, T=wl.T,
                 method="ndft", precision="split_bf16")
     ref = oracle_s("gaussian", x, y, w, r["xi"], sigma, "ndft", wl.n_coeff, wl.T)
-    err = sliced.rel_l2(r["s"], ref)
-    note(f"  rel err vs oracle {err:.3e}")
-    assert err <= MIXED_TOL
+    assert_parity(r["s"], ref, MIXED_TOL)
 
 
 def test_split_bf16_gauss_nfft_workload_reduced():
@@ -92,9 +91,7 @@ def test_split_bf16_gauss_nfft_workload_reduced():
     r = run_gpu("gaussian", x, y, w, wl.P, seed=wl.dir_seed, sigma=sigma, n_coeff=wl.n_coeff, T=wl.T,
                 method="nfft", oversample=2, window_m=6, precision="split_bf16")
     ref = oracle_s("gaussian", x, y, w, r["xi"], sigma, "nfft", wl.n_coeff, wl.T)
-    err = sliced.rel_l2(r["s"], ref)
-    note(f"  rel err vs oracle {err:.3e}")
-    assert err <= MIXED_TOL
+    assert_parity(r["s"], ref, MIXED_TOL)
 
 
 def test_split_bf16_laplace_workload_reduced():
@@ -106,6 +103,4 @@ def test_split_bf16_laplace_workload_reduced():
                 probe=True, precision="split_bf16")
     _check_perm(r["z"], r["perm"])
     ref = oracle_s("laplacian", x, y, w, r["xi"], sigma, "nfft", wl.n_coeff, wl.T)
-    err = sliced.rel_l2(r["s"], ref)
-    note(f"  rel err vs oracle {err:.3e}")
-    assert err <= MIXED_TOL
+    assert_parity(r["s"], ref, MIXED_TOL)
