@@ -211,6 +211,23 @@ ksum_status ksum_execute_probe_f64in(ksum_plan *plan, const double *x, int64_t N
                                      const double *w, float *s, void *ws, size_t ws_bytes, void *stream,
                                      const ksum_probe *probe);
 
+/* Forward sum for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc) and so cannot
+ * provide the workspace of ksum_execute.  Same arguments and result as
+ * ksum_execute without ws / ws_bytes: the workspace is a static device array of
+ * KSUM_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held from the first
+ * use on that GPU until the process ends.  The slices run in batches of the
+ * plan's batch size or fewer, as many as fit the array; the result does not depend
+ * on the batch size.  Allocates nothing (no hipMalloc, hipFree or allocating
+ * library call).  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other threads, other plans) race and must be
+ * ordered by the caller; each call writes every part of the array it reads before
+ * reading it.  EWORKSPACE if one slice of N sources and M targets needs more than
+ * the array holds; other errors as for ksum_execute. */
+#define KSUM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+ksum_status ksum_execute_noalloc(ksum_plan *plan, const float *x, int64_t N, const float *y, int64_t M,
+                                 const float *w, float *s, void *stream);
+
 /* Workspace bytes ksum_backward needs for N sources and M targets. */
 ksum_status ksum_backward_workspace_size(const ksum_plan *plan, int64_t N, int64_t M, size_t *bytes);
 

@@ -29,6 +29,7 @@ KSUM_1D_AUTO, KSUM_1D_NDFT, KSUM_1D_NFFT, KSUM_1D_SORT = 0, 1, 2, 3
 KSUM_FP32, KSUM_SPLIT_BF16 = 0, 1
 PRECISIONS = {"fp32": KSUM_FP32, "split_bf16": KSUM_SPLIT_BF16}
 KSUM_OK, KSUM_EINVAL, KSUM_EUNSUPPORTED, KSUM_ENOMEM, KSUM_EWORKSPACE, KSUM_ENONFINITE, KSUM_EDEVICE = range(7)
+KSUM_NOALLOC_SCRATCH_BYTES = 256 << 20      # static scratch of ksum_execute_noalloc, per GPU
 
 KERNELS = {"gaussian": KSUM_GAUSSIAN, "laplacian": KSUM_LAPLACIAN, "negdist": KSUM_NEGDIST, "matern": KSUM_MATERN}
 METHODS = {"auto": KSUM_1D_AUTO, "ndft": KSUM_1D_NDFT, "nfft": KSUM_1D_NFFT, "sort": KSUM_1D_SORT}
@@ -87,6 +88,7 @@ _sigs = {
                                           _P, ctypes.POINTER(ksum_probe)]),
     "ksum_execute_probe_f64in": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P,
                                                 ctypes.c_size_t, _P, ctypes.POINTER(ksum_probe)]),
+    "ksum_execute_noalloc": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P]),
     "ksum_backward_workspace_size": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64,
                                                     ctypes.POINTER(ctypes.c_size_t)]),
     "ksum_backward": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P, _P, _P, _P,
@@ -223,6 +225,10 @@ def ksum_execute_probe_f64in(plan: int, x: int, N: int, y: int, M: int, w: int, 
     _check(_lib.ksum_execute_probe_f64in(plan, x, N, y, M, w, s, ws, ws_bytes, stream,
                                          ctypes.byref(probe) if probe is not None else None),
            "ksum_execute_probe_f64in")
+
+
+def ksum_execute_noalloc(plan: int, x: int, N: int, y: int, M: int, w: int, s: int, stream: int) -> None:
+    _check(_lib.ksum_execute_noalloc(plan, x, N, y, M, w, s, stream), "ksum_execute_noalloc")
 
 
 def ksum_backward_workspace_size(plan: int, N: int, M: int) -> int:

@@ -141,7 +141,8 @@ struct Layout {
 
 constexpr int kWsumBlocks = 64;
 
-Layout make_layout(const ksum_plan &plan, int64_t N, int64_t M);
+// batch > 0 sets the slices per batch (at most the plan's own batch size) in place of the plan's
+Layout make_layout(const ksum_plan &plan, int64_t N, int64_t M, int32_t batch = 0);
 
 // ---------------------------------------------------------------------------
 // Launch wrappers (defined in the .hip files).  All take the batch's first

@@ -383,7 +383,9 @@ __global__ __launch_bounds__(256) void nfft_interp_accum_kernel(FourierArgs a, A
   const bool live = m < a.M;
   const float fn = (float)a.n;
   float *SP = G + (size_t)sb * a.W;
-  double acc = 0.0;
+  // the running FP64 sum continues from the previous batch, so the additions run in
+  // slice order whatever the batch size
+  double acc = (!DERIV && live && !c.first) ? c.sacc[m] : 0.0;
   for (int pb = 0; pb < a.nsl; pb += sb) {
     const int np = min(sb, a.nsl - pb);
     __syncthreads();
@@ -451,9 +453,8 @@ __global__ __launch_bounds__(256) void nfft_interp_accum_kernel(FourierArgs a, A
     }
   }
   if (DERIV || !live) return;
-  const double v = (c.first ? 0.0 : c.sacc[m]) + acc;
-  if (c.last) c.s[m] = (float)(v * c.invP);
-  else c.sacc[m] = v;
+  if (c.last) c.s[m] = (float)(acc * c.invP);
+  else c.sacc[m] = acc;
 }
 
 template <int MW, int DEG, int SH>

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -110,13 +111,14 @@ static ksum_status validate(int32_t d, int32_t P, ksum_kernel kernel, const ksum
   return KSUM_OK;
 }
 
-Layout make_layout(const ksum_plan &pl, int64_t N, int64_t M) {
+Layout make_layout(const ksum_plan &pl, int64_t N, int64_t M, int32_t batch) {
   Layout y;
   y.N = N;
   y.M = M;
   y.L = N + M;
   y.B = pl.params.slice_batch > 0 ? std::min(pl.params.slice_batch, pl.P) : pl.P;
   y.B = std::min(y.B, kMaxBatch);
+  if (batch > 0) y.B = std::min(y.B, batch);
   const int64_t B = y.B;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -543,6 +545,77 @@ ksum_status ksum_execute_probe_f64in(ksum_plan *plan, const double *x, int64_t N
                                      const double *w, float *s, void *ws, size_t ws_bytes, void *stream,
                                      const ksum_probe *probe) {
   return execute_impl(plan, x, N, y, M, w, true, s, ws, ws_bytes, stream, probe);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Static scratch of ksum_execute_noalloc.  Every device the library runs on holds
+// its own copy of this array (part of the code object loaded there) until the
+// process ends.  Host code never passes the array's name to a kernel: the name is
+// a host-side stand-in, and the device address of a device's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[KSUM_NOALLOC_SCRATCH_BYTES];
+
+namespace ksum {
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the scratch array on `dev`, which must be the current device.
+static ksum_status scratch_address(int dev, char **out) {
+  if (dev < 0 || dev >= kMaxScratchDevices) return fail(KSUM_EUNSUPPORTED, "device ordinal beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(KSUM_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<char *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return KSUM_OK;
+}
+
+}  // namespace ksum
+
+extern "C" {
+
+ksum_status ksum_execute_noalloc(ksum_plan *plan, const float *x, int64_t N, const float *y, int64_t M,
+                                 const float *w, float *s, void *stream) {
+  if (!plan) return fail(KSUM_EINVAL, "plan is NULL");
+  if (!x || !y || !w || !s) return fail(KSUM_EINVAL, "null device pointer");
+  if (N < 1 || M < 1) return fail(KSUM_EINVAL, "N and M must be >= 1");
+  if (N + M > 0x7fffffffLL) return fail(KSUM_EUNSUPPORTED, "N + M must be < 2^31");
+  // the largest slice batch (at most the plan's) whose workspace fits the scratch; the
+  // result does not depend on the batch size
+  const size_t cap = KSUM_NOALLOC_SCRATCH_BYTES;
+  const Layout one = make_layout(*plan, N, M, 1);
+  if (one.total > cap)
+    return fail(KSUM_EWORKSPACE, "N + M too large for the static scratch: one slice per batch needs " +
+                                     std::to_string(one.total) + " bytes, the scratch holds " + std::to_string(cap));
+  int32_t lo = 1, hi = make_layout(*plan, N, M).B;
+  while (lo < hi) {
+    const int32_t mid = lo + (hi - lo + 1) / 2;
+    if (make_layout(*plan, N, M, mid).total <= cap) lo = mid;
+    else hi = mid - 1;
+  }
+  const Layout lay = make_layout(*plan, N, M, lo);
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  if (prev != plan->params.device && hipSetDevice(plan->params.device) != hipSuccess)
+    return fail(KSUM_EDEVICE, "hipSetDevice failed");
+  char *ws = nullptr;
+  ksum_status st = scratch_address(plan->params.device, &ws);
+  if (st == KSUM_OK) {
+    const hipError_t e = run_pipeline(plan, lay, x, y, w, false, s, false, nullptr, 0, ws,
+                                      static_cast<hipStream_t>(stream), nullptr);
+    if (e != hipSuccess) st = fail(KSUM_EDEVICE, std::string("HIP launch failed: ") + hipGetErrorString(e));
+  }
+  if (prev != plan->params.device) (void)hipSetDevice(prev);
+  return st;
 }
 
 ksum_status ksum_backward_workspace_size(const ksum_plan *plan, int64_t N, int64_t M, size_t *bytes) {
