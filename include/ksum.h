@@ -84,7 +84,7 @@ typedef enum {
   KSUM_EUNSUPPORTED = 2,  /* valid but not supported (e.g. a method the kernel cannot use) */
   KSUM_ENOMEM = 3,        /* device or host allocation failed at plan time */
   KSUM_EWORKSPACE = 4,    /* workspace smaller than ksum_workspace_size() */
-  KSUM_ENONFINITE = 5,    /* reserved: non-finite input detected */
+  KSUM_ENONFINITE = 5,    /* an input holds a NaN or an infinity (only with params.check_finite) */
   KSUM_EDEVICE = 6        /* HIP runtime error, or no usable device */
 } ksum_status;
 
@@ -106,7 +106,13 @@ typedef enum {
  *   precision   ksum_precision
  *   slice_batch slices per batch B (0 = all P); bounds the workspace (Remark on
  *               memory requirements and batching, Sec. 4.4)
- *   device      HIP device ordinal the plan is created on */
+ *   device      HIP device ordinal the plan is created on
+ *   check_finite 1: ksum_execute*, ksum_execute_noalloc and ksum_backward first pass once
+ *               over their inputs (x, y, w and grad_s) and wait for the result; a NaN or
+ *               an infinity makes the call return KSUM_ENONFINITE before any other work,
+ *               with no output written.  The wait makes such calls synchronous with
+ *               their stream.  0 (default): no check; a non-finite input gives
+ *               unspecified results (the sort places a NaN projection last). */
 typedef struct {
   double sigma;
   uint64_t seed;
@@ -120,6 +126,7 @@ typedef struct {
   int32_t precision;
   int32_t slice_batch;
   int32_t device;
+  int32_t check_finite;
 } ksum_params;
 
 /* Optional intermediate outputs of ksum_execute_probe (each pointer may be NULL).
@@ -284,6 +291,10 @@ typedef struct {
   float *s;                  /* device float[M] output */
   const float *grad_s;       /* device float[M] upstream gradient, or NULL for no backward */
   float *grad_x, *grad_y, *grad_w;   /* backward outputs (each may be NULL) */
+  void *ready_event;         /* hipEvent_t recorded after the work that writes x, y, w, grad_s; the
+                                request's kernels wait for it.  NULL: the inputs must be complete on
+                                the device when ksum_server_submit is called.  The event must not be
+                                recorded again or destroyed before the request's completion is polled */
 } ksum_request;
 
 typedef struct {
@@ -317,7 +328,9 @@ ksum_status ksum_server_destroy(ksum_server *server);
  * on its stream around every kernel it launches (a few microseconds of overhead
  * per kernel); ksum_stage_times synchronises with the last event and returns,
  * for each stage, the accumulated milliseconds and the number of launches since
- * timing was enabled.  Not thread-safe: time one execution stream at a time.
+ * timing was enabled.  The plan holds 16384 events between two reads: launches
+ * beyond them are not timed, and the next ksum_stage_times still fills its outputs
+ * but returns KSUM_EWORKSPACE.  Not thread-safe: time one execution stream at a time.
  * Stages are numbered 0..ksum_stage_count()-1 and named by ksum_stage_name(). */
 ksum_status ksum_set_timing(ksum_plan *plan, int32_t enable);
 ksum_status ksum_stage_times(ksum_plan *plan, double *ms_out, int64_t *calls_out);

@@ -40,7 +40,7 @@ class ksum_params(ctypes.Structure):
                 ("directions", ctypes.POINTER(ctypes.c_double)), ("n_coeff", ctypes.c_int32),
                 ("coeff_eps", ctypes.c_double), ("T", ctypes.c_double), ("oversample", ctypes.c_int32),
                 ("window_m", ctypes.c_int32), ("method", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("slice_batch", ctypes.c_int32), ("device", ctypes.c_int32)]
+                ("slice_batch", ctypes.c_int32), ("device", ctypes.c_int32), ("check_finite", ctypes.c_int32)]
 
 
 class ksum_probe(ctypes.Structure):
@@ -53,7 +53,8 @@ class ksum_request(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_uint64), ("d", ctypes.c_int32), ("P", ctypes.c_int32), ("kernel", ctypes.c_int),
                 ("params", ksum_params), ("x", ctypes.c_void_p), ("N", ctypes.c_int64), ("y", ctypes.c_void_p),
                 ("M", ctypes.c_int64), ("w", ctypes.c_void_p), ("s", ctypes.c_void_p), ("grad_s", ctypes.c_void_p),
-                ("grad_x", ctypes.c_void_p), ("grad_y", ctypes.c_void_p), ("grad_w", ctypes.c_void_p)]
+                ("grad_x", ctypes.c_void_p), ("grad_y", ctypes.c_void_p), ("grad_w", ctypes.c_void_p),
+                ("ready_event", ctypes.c_void_p)]
 
 
 class ksum_completion(ctypes.Structure):
@@ -416,7 +417,13 @@ class Server:
         r.grad_x = gx.data_ptr() if gx is not None else None
         r.grad_y = gy.data_ptr() if gy is not None else None
         r.grad_w = gw.data_ptr() if gw is not None else None
-        self._keep[tag] = (x, y, w, s, grad_s, gx, gy, gw)
+        # the request waits for the work the current stream has queued so far (which may
+        # still be writing its inputs)
+        import torch
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(x.device))
+        r.ready_event = ev.cuda_event
+        self._keep[tag] = (x, y, w, s, grad_s, gx, gy, gw, ev)
         _check(_lib.ksum_server_submit(self.handle, ctypes.byref(r)), "ksum_server_submit")
 
     def poll(self, max_out: int = 256):

@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -56,11 +57,14 @@ enum StageId {
   ST_SORT_FALLBACK, ST_BACKPROJ, ST_COUNT
 };
 
+constexpr int kTimerEvents = 16384;   // timing marks held between two reads of the stage times
+
 struct Timer {
   int device = 0;
   std::vector<hipEvent_t> ev;
   std::vector<int> ids;
   int used = 0;
+  long long dropped = 0;   // marks that found every event in use since the last read
   double ms[ST_COUNT] = {};
   long long calls[ST_COUNT] = {};
 };
@@ -95,6 +99,15 @@ struct ksum_plan {
   float2 *d_twiddle = nullptr;   // [n_grid] exp(-2 pi i j / n)
   double *d_costab = nullptr;    // [lap_L] cos(2 pi j / lap_L)
   ksum::Timer *timer = nullptr;  // stage timing (diagnostic), null when off
+  // Completion of the plan's work for ksum_plan_destroy: one event per stream that ran
+  // the plan, re-recorded after each call on that stream.  Streams beyond the slots set
+  // use_overflow, and destroy then waits for the whole device.
+  static constexpr int kUseSlots = 32;
+  std::mutex use_mu;
+  hipStream_t use_stream[kUseSlots] = {};
+  hipEvent_t use_event[kUseSlots] = {};
+  int n_use = 0;
+  bool use_overflow = false;
 };
 
 namespace ksum {
@@ -136,6 +149,7 @@ struct Layout {
   size_t off_keys2 = 0;          // uint64[B][L] scratch of the large-group sort
   size_t off_desc = 0;           // int4[B][sort_groups] group descriptors
   size_t off_fail = 0;           // uint32 count (+63 pad) and uint32[B][sort_groups] fallback list
+  size_t off_flag = 0;           // uint32 non-finite input flag (opt-in check)
   size_t total = 0;
 };
 
@@ -176,7 +190,11 @@ template <typename T> inline T *wsp(const ExecArgs &a, size_t off) {
 // mark is attributed to `stage` (stage < 0 closes the interval).
 inline void mark(const ksum_plan *plan, hipStream_t stream, int stage) {
   Timer *t = plan->timer;
-  if (!t || t->used >= (int)t->ev.size()) return;
+  if (!t) return;
+  if (t->used >= (int)t->ev.size()) {
+    ++t->dropped;
+    return;
+  }
   if (hipEventRecord(t->ev[t->used], stream) == hipSuccess) t->ids[t->used++] = stage;
 }
 
@@ -196,6 +214,7 @@ hipError_t launch_accumulate(const ExecArgs &a, float *s, bool first, bool last)
 hipError_t launch_nfft_interp(const ExecArgs &a, float *s, bool first, bool last);
 hipError_t launch_deriv_gather(const ExecArgs &a);
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t stream);
+hipError_t launch_check_finite(const void *p, int64_t n, bool f64, uint32_t *flag, hipStream_t stream);
 hipError_t launch_backproject(const ksum_plan &plan, const float *D, int64_t ldd, int64_t R, const float *scale,
                               double factor, float *out, hipStream_t stream);
 

@@ -114,4 +114,23 @@ hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// Opt-in input check: sets *flag to 1 if any of the n values is NaN or infinite.  The
+// flag is cleared by the caller (a fill kernel) before the first check of a call.
+template <typename T>
+__global__ __launch_bounds__(256) void check_finite_kernel(const T *__restrict__ p, int64_t n,
+                                                          uint32_t *__restrict__ flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(p[i]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) *flag = 1u;
+}
+
+hipError_t launch_check_finite(const void *p, int64_t n, bool f64, uint32_t *flag, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
+  if (f64) check_finite_kernel<double><<<grid, 256, 0, stream>>>(static_cast<const double *>(p), n, flag);
+  else check_finite_kernel<float><<<grid, 256, 0, stream>>>(static_cast<const float *>(p), n, flag);
+  return hipGetLastError();
+}
+
 }  // namespace ksum

@@ -6,8 +6,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -86,6 +88,7 @@ static ksum_status validate(int32_t d, int32_t P, ksum_kernel kernel, const ksum
     return fail(KSUM_EINVAL, "unknown precision");
   if (p.slice_batch < 0) return fail(KSUM_EINVAL, "slice_batch must be >= 0");
   if (p.device < 0) return fail(KSUM_EINVAL, "device must be >= 0");
+  if (p.check_finite != 0 && p.check_finite != 1) return fail(KSUM_EINVAL, "check_finite must be 0 or 1");
   if (kernel == KSUM_NEGDIST) {
     if (p.method != KSUM_1D_AUTO && p.method != KSUM_1D_SORT)
       return fail(KSUM_EUNSUPPORTED, "the negative distance kernel uses the sort method");
@@ -168,6 +171,7 @@ Layout make_layout(const ksum_plan &pl, int64_t N, int64_t M, int32_t batch) {
     y.off_desc = take((size_t)B * y.sort_groups * sizeof(int4));
     y.off_fail = take((64 + (size_t)B * y.sort_groups) * sizeof(uint32_t));
   }
+  y.off_flag = take(64);
   y.total = o;
   return y;
 }
@@ -186,6 +190,7 @@ static void fill_defaults(ksum_kernel kernel, ksum_params *p) {
   p->precision = KSUM_FP32;
   p->slice_batch = 0;
   p->device = 0;
+  p->check_finite = 0;
 }
 
 static void free_timer(ksum_plan *pl) {
@@ -195,16 +200,69 @@ static void free_timer(ksum_plan *pl) {
   pl->timer = nullptr;
 }
 
+// The library's own stream on a device (non-blocking, default priority), made at the
+// first use: plan tables are allocated, uploaded and freed in its order, so that
+// releasing a plan waits for the plan's own work and not for the whole device.
+static std::mutex g_stream_mu;
+static hipStream_t g_lib_stream[64] = {};
+
+static hipStream_t library_stream(int dev) {
+  if (dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(g_stream_mu);
+  if (!g_lib_stream[dev] && hipStreamCreateWithFlags(&g_lib_stream[dev], hipStreamNonBlocking) != hipSuccess)
+    g_lib_stream[dev] = nullptr;
+  return g_lib_stream[dev];
+}
+
+// Device copy of a host table, allocated from the device's stream-ordered pool.
+static hipError_t upload(hipStream_t ls, void **dst, const void *src, size_t bytes) {
+  hipError_t e = hipMallocAsync(dst, bytes, ls);
+  if (e == hipSuccess) e = hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, ls);
+  if (e == hipSuccess) e = hipStreamSynchronize(ls);
+  return e;
+}
+
+// Records that the plan's work was enqueued on `stream` (after every call that launches).
+static void note_use(ksum_plan *pl, hipStream_t stream) {
+  std::lock_guard<std::mutex> lock(pl->use_mu);
+  int i = 0;
+  while (i < pl->n_use && pl->use_stream[i] != stream) ++i;
+  if (i == pl->n_use) {
+    if (pl->n_use == ksum_plan::kUseSlots ||
+        hipEventCreateWithFlags(&pl->use_event[i], hipEventDisableTiming) != hipSuccess) {
+      pl->use_overflow = true;
+      return;
+    }
+    pl->use_stream[i] = stream;
+    ++pl->n_use;
+  }
+  if (hipEventRecord(pl->use_event[i], stream) != hipSuccess) pl->use_overflow = true;
+}
+
+// Releases a plan's tables in the library stream's order after the plan's own work
+// (the device must be current).
 static void free_plan(ksum_plan *pl) {
   if (!pl) return;
   free_timer(pl);
-  if (pl->d_dirs) (void)hipFree(pl->d_dirs);
-  if (pl->d_dirs_hi) (void)hipFree(pl->d_dirs_hi);
-  if (pl->d_dirsT) (void)hipFree(pl->d_dirsT);
-  if (pl->d_dirs_lo) (void)hipFree(pl->d_dirs_lo);
-  if (pl->d_deconv) (void)hipFree(pl->d_deconv);
-  if (pl->d_twiddle) (void)hipFree(pl->d_twiddle);
-  if (pl->d_costab) (void)hipFree(pl->d_costab);
+  void *tabs[] = {pl->d_dirs, pl->d_dirs_hi, pl->d_dirs_lo, pl->d_dirsT, pl->d_deconv, pl->d_twiddle,
+                  pl->d_costab};
+  bool on_device = pl->n_use > 0;
+  for (void *t : tabs) on_device |= t != nullptr;
+  if (!on_device) {
+    delete pl;
+    return;
+  }
+  hipStream_t ls = library_stream(pl->params.device);
+  if (pl->use_overflow || !ls) (void)hipDeviceSynchronize();
+  for (int i = 0; i < pl->n_use; ++i) {
+    if (ls) (void)hipStreamWaitEvent(ls, pl->use_event[i], 0);
+    (void)hipEventDestroy(pl->use_event[i]);
+  }
+  for (void *t : tabs) {
+    if (!t) continue;
+    if (ls) (void)hipFreeAsync(t, ls);
+    else (void)hipFree(t);
+  }
   delete pl;
 }
 
@@ -336,21 +394,25 @@ ksum_status ksum_plan_create(int32_t d, int32_t P, ksum_kernel kernel, const ksu
     (void)hipSetDevice(prev);
     return fail(s, what);
   };
+  hipStream_t ls = library_stream(pl->params.device);
+  if (!ls) return dev_fail(KSUM_EDEVICE, "could not create the library stream");
+  auto up = [&](auto **dst, const void *src, size_t bytes) {
+    void *p = nullptr;
+    const hipError_t e = upload(ls, &p, src, bytes);
+    *dst = static_cast<std::remove_reference_t<decltype(**dst)> *>(p);
+    return e == hipSuccess;
+  };
   // directions, FP32, zero padded to [P_pad][d_pad]
   std::vector<float> hd((size_t)pl->P_pad * pl->d_pad, 0.f);
   for (int32_t p = 0; p < P; ++p)
     for (int32_t i = 0; i < d; ++i) hd[(size_t)p * pl->d_pad + i] = (float)pl->dirs[(size_t)p * d + i];
-  if (hipMalloc(&pl->d_dirs, hd.size() * sizeof(float)) != hipSuccess) return dev_fail(KSUM_ENOMEM, "hipMalloc");
-  if (hipMemcpy(pl->d_dirs, hd.data(), hd.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
-    return dev_fail(KSUM_EDEVICE, "hipMemcpy");
+  if (!up(&pl->d_dirs, hd.data(), hd.size() * sizeof(float))) return dev_fail(KSUM_ENOMEM, "device allocation");
   {
     // transposed FP32 directions [d][Pk] for the back-projection of the backward pass
     std::vector<float> ht((size_t)d * pl->Pk, 0.f);
     for (int32_t p = 0; p < P; ++p)
       for (int32_t i = 0; i < d; ++i) ht[(size_t)i * pl->Pk + p] = (float)pl->dirs[(size_t)p * d + i];
-    if (hipMalloc(&pl->d_dirsT, ht.size() * sizeof(float)) != hipSuccess) return dev_fail(KSUM_ENOMEM, "hipMalloc");
-    if (hipMemcpy(pl->d_dirsT, ht.data(), ht.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
-      return dev_fail(KSUM_EDEVICE, "hipMemcpy");
+    if (!up(&pl->d_dirsT, ht.data(), ht.size() * sizeof(float))) return dev_fail(KSUM_ENOMEM, "device allocation");
   }
   if (pl->params.precision == KSUM_SPLIT_BF16) {
     // hi = bf16(xi), lo = bf16(xi - hi) of the FP32 directions, round to nearest even
@@ -360,11 +422,8 @@ ksum_status ksum_plan_create(int32_t d, int32_t P, ksum_kernel kernel, const ksu
       hl[i] = bf16_rne(hd[i] - bf16_to_float(hh[i]));
     }
     const size_t nb = hd.size() * sizeof(uint16_t);
-    if (hipMalloc(&pl->d_dirs_hi, nb) != hipSuccess || hipMalloc(&pl->d_dirs_lo, nb) != hipSuccess)
-      return dev_fail(KSUM_ENOMEM, "hipMalloc");
-    if (hipMemcpy(pl->d_dirs_hi, hh.data(), nb, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(pl->d_dirs_lo, hl.data(), nb, hipMemcpyHostToDevice) != hipSuccess)
-      return dev_fail(KSUM_EDEVICE, "hipMemcpy");
+    if (!up(&pl->d_dirs_hi, hh.data(), nb) || !up(&pl->d_dirs_lo, hl.data(), nb))
+      return dev_fail(KSUM_ENOMEM, "device allocation");
   }
   if (pl->method == KSUM_1D_NFFT) {
     const int n = pl->n_grid, m = pl->params.window_m, os = pl->params.oversample;
@@ -381,19 +440,14 @@ ksum_status ksum_plan_create(int32_t d, int32_t P, ksum_kernel kernel, const ksu
       const double ang = -2.0 * M_PI * (double)j / (double)n;
       tw[j] = make_float2((float)std::cos(ang), (float)std::sin(ang));
     }
-    if (hipMalloc(&pl->d_deconv, dc.size() * sizeof(float)) != hipSuccess ||
-        hipMalloc(&pl->d_twiddle, tw.size() * sizeof(float2)) != hipSuccess)
-      return dev_fail(KSUM_ENOMEM, "hipMalloc");
-    if (hipMemcpy(pl->d_deconv, dc.data(), dc.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(pl->d_twiddle, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
-      return dev_fail(KSUM_EDEVICE, "hipMemcpy");
+    if (!up(&pl->d_deconv, dc.data(), dc.size() * sizeof(float)) ||
+        !up(&pl->d_twiddle, tw.data(), tw.size() * sizeof(float2)))
+      return dev_fail(KSUM_ENOMEM, "device allocation");
   }
   if (pl->lap_L > 0) {
     std::vector<double> ct(pl->lap_L);
     for (int j = 0; j < pl->lap_L; ++j) ct[j] = std::cos(2.0 * M_PI * (double)j / (double)pl->lap_L);
-    if (hipMalloc(&pl->d_costab, ct.size() * sizeof(double)) != hipSuccess) return dev_fail(KSUM_ENOMEM, "hipMalloc");
-    if (hipMemcpy(pl->d_costab, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
-      return dev_fail(KSUM_EDEVICE, "hipMemcpy");
+    if (!up(&pl->d_costab, ct.data(), ct.size() * sizeof(double))) return dev_fail(KSUM_ENOMEM, "device allocation");
   }
   (void)hipSetDevice(prev);
   *out = pl;
@@ -405,7 +459,6 @@ ksum_status ksum_plan_destroy(ksum_plan *plan) {
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(plan->params.device);
-  (void)hipDeviceSynchronize();
   free_plan(plan);
   (void)hipSetDevice(prev);
   return KSUM_OK;
@@ -478,6 +531,29 @@ static hipError_t run_pipeline(ksum_plan *plan, const Layout &lay, const void *x
   return e;
 }
 
+// The opt-in input check (params.check_finite): one pass over each array on the execution
+// stream, then a wait for the flag it leaves in the workspace.  Runs before any other
+// kernel of the call, so a call refused with KSUM_ENONFINITE writes no output.
+struct CheckedArray {
+  const void *p;
+  int64_t n;
+  bool f64;
+};
+
+static ksum_status check_inputs(std::initializer_list<CheckedArray> arrays, char *ws, const Layout &lay,
+                                hipStream_t stream) {
+  uint32_t *flag = reinterpret_cast<uint32_t *>(ws + lay.off_flag);
+  hipError_t e = launch_fill_zero(reinterpret_cast<float *>(flag), 1, stream);
+  for (const CheckedArray &a : arrays)
+    if (e == hipSuccess) e = launch_check_finite(a.p, a.n, a.f64, flag, stream);
+  uint32_t seen = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&seen, flag, sizeof(seen), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return fail(KSUM_EDEVICE, std::string("input check failed: ") + hipGetErrorString(e));
+  if (seen) return fail(KSUM_ENONFINITE, "an input holds a NaN or an infinity");
+  return KSUM_OK;
+}
+
 static ksum_status check_exec_args(ksum_plan *plan, const void *x, int64_t N, const void *y, int64_t M,
                                    const void *w, const void *ws) {
   if (!plan) return fail(KSUM_EINVAL, "plan is NULL");
@@ -500,9 +576,20 @@ static ksum_status execute_impl(ksum_plan *plan, const void *x, int64_t N, const
   (void)hipGetDevice(&prev);
   if (prev != plan->params.device && hipSetDevice(plan->params.device) != hipSuccess)
     return fail(KSUM_EDEVICE, "hipSetDevice failed");
-  const hipError_t e = run_pipeline(plan, lay, x, y, w, f64, s, false, nullptr, 0, static_cast<char *>(ws),
-                                    static_cast<hipStream_t>(stream), probe);
+  ksum_status cst = KSUM_OK;
+  if (plan->params.check_finite) {
+    const int64_t d = plan->d;
+    cst = check_inputs({{x, N * d, f64}, {y, M * d, f64}, {w, N, f64}}, static_cast<char *>(ws), lay,
+                       static_cast<hipStream_t>(stream));
+  }
+  hipError_t e = hipSuccess;
+  if (cst == KSUM_OK) {
+    e = run_pipeline(plan, lay, x, y, w, f64, s, false, nullptr, 0, static_cast<char *>(ws),
+                     static_cast<hipStream_t>(stream), probe);
+    note_use(plan, static_cast<hipStream_t>(stream));
+  }
   if (prev != plan->params.device) (void)hipSetDevice(prev);
+  if (cst != KSUM_OK) return cst;
   if (e != hipSuccess) return fail(KSUM_EDEVICE, std::string("HIP launch failed: ") + hipGetErrorString(e));
   return KSUM_OK;
 }
@@ -609,9 +696,15 @@ ksum_status ksum_execute_noalloc(ksum_plan *plan, const float *x, int64_t N, con
     return fail(KSUM_EDEVICE, "hipSetDevice failed");
   char *ws = nullptr;
   ksum_status st = scratch_address(plan->params.device, &ws);
+  if (st == KSUM_OK && plan->params.check_finite) {
+    const int64_t d = plan->d;
+    st = check_inputs({{x, N * d, false}, {y, M * d, false}, {w, N, false}}, ws, lay,
+                      static_cast<hipStream_t>(stream));
+  }
   if (st == KSUM_OK) {
     const hipError_t e = run_pipeline(plan, lay, x, y, w, false, s, false, nullptr, 0, ws,
                                       static_cast<hipStream_t>(stream), nullptr);
+    note_use(plan, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) st = fail(KSUM_EDEVICE, std::string("HIP launch failed: ") + hipGetErrorString(e));
   }
   if (prev != plan->params.device) (void)hipSetDevice(prev);
@@ -641,6 +734,15 @@ ksum_status ksum_backward(ksum_plan *plan, const float *x, int64_t N, const floa
     return fail(KSUM_EDEVICE, "hipSetDevice failed");
   char *wsc = static_cast<char *>(ws);
   const hipStream_t sm = static_cast<hipStream_t>(stream);
+  if (plan->params.check_finite) {
+    const int64_t d = plan->d;
+    const ksum_status cst = check_inputs({{x, N * d, false}, {y, M * d, false}, {w, N, false}, {grad_s, M, false}},
+                                         wsc, make_layout(*plan, N, M), sm);
+    if (cst != KSUM_OK) {
+      if (prev != plan->params.device) (void)hipSetDevice(prev);
+      return cst;
+    }
+  }
   const int64_t ldd = plan->Pk;
   const double invP = 1.0 / (double)plan->P;
   float *Dy = reinterpret_cast<float *>(wsc + bo.dy);
@@ -731,6 +833,7 @@ ksum_status ksum_backward(ksum_plan *plan, const float *x, int64_t N, const floa
     e = launch_backproject(*plan, Dx, ldd, N, w, invP, grad_x, sm);
   }
   mark(plan, sm, -1);
+  note_use(plan, sm);
   if (prev != plan->params.device) (void)hipSetDevice(prev);
   if (e != hipSuccess) return fail(KSUM_EDEVICE, std::string("HIP launch failed: ") + hipGetErrorString(e));
   return KSUM_OK;
@@ -761,8 +864,8 @@ ksum_status ksum_set_timing(ksum_plan *plan, int32_t enable) {
       st = fail(KSUM_ENOMEM, "host allocation failed");
     } else {
       t->device = plan->params.device;
-      t->ev.resize(4096);
-      t->ids.resize(4096);
+      t->ev.resize(kTimerEvents);
+      t->ids.resize(kTimerEvents);
       for (auto &e : t->ev) {
         if (hipEventCreate(&e) != hipSuccess) {
           e = nullptr;
@@ -802,6 +905,13 @@ ksum_status ksum_stage_times(ksum_plan *plan, double *ms_out, int64_t *calls_out
   for (int i = 0; i < ST_COUNT; ++i) {
     ms_out[i] = t->ms[i];
     if (calls_out) calls_out[i] = t->calls[i];
+  }
+  if (t->dropped > 0) {
+    const long long n = t->dropped;
+    t->dropped = 0;
+    return fail(KSUM_EWORKSPACE, std::to_string(n) + " timing marks were dropped (more than " +
+                                     std::to_string(kTimerEvents) + " launches between two reads); the times "
+                                     "returned miss them");
   }
   return KSUM_OK;
 }

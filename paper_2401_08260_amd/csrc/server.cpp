@@ -19,6 +19,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "internal.h"
@@ -89,15 +90,18 @@ class Arena {
   std::map<size_t, size_t> free_;
 };
 
+// A plan is shared by requests whose (d, P, kernel) and parameter fields agree; the
+// fields are compared one by one (a struct's padding bytes carry no value).  The
+// directions pointer and the device are not part of a request's plan.
 struct PlanKey {
   int32_t d, P, kernel;
   ksum_params params;
-  bool operator<(const PlanKey &o) const {
-    if (d != o.d) return d < o.d;
-    if (P != o.P) return P < o.P;
-    if (kernel != o.kernel) return kernel < o.kernel;
-    return std::memcmp(&params, &o.params, sizeof(params)) < 0;
+  auto fields() const {
+    const ksum_params &q = params;
+    return std::make_tuple(d, P, kernel, q.sigma, q.seed, q.n_coeff, q.coeff_eps, q.T, q.oversample, q.window_m,
+                           q.method, q.precision, q.slice_batch, q.check_finite);
   }
+  bool operator<(const PlanKey &o) const { return fields() < o.fields(); }
 };
 
 struct Pending {
@@ -217,7 +221,12 @@ struct ksum_server {
       sl.t_start = now_s();
       const ksum_request &r = sl.job.req;
       void *ws = arena.ptr(off);
-      int32_t status = ksum_execute(pl, r.x, r.N, r.y, r.M, r.w, r.s, ws, bytes, sl.stream);
+      int32_t status = KSUM_OK;
+      // the inputs are complete once the caller's event has fired
+      if (r.ready_event && hipStreamWaitEvent(sl.stream, static_cast<hipEvent_t>(r.ready_event), 0) != hipSuccess)
+        status = KSUM_EDEVICE;
+      if (status == KSUM_OK)
+        status = ksum_execute(pl, r.x, r.N, r.y, r.M, r.w, r.s, ws, bytes, sl.stream);
       if (status == KSUM_OK && r.grad_s)
         status = ksum_backward(pl, r.x, r.N, r.y, r.M, r.w, r.grad_s, r.grad_x, r.grad_y, r.grad_w, ws, bytes,
                                sl.stream);

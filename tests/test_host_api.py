@@ -72,6 +72,9 @@ def test_validation_status_codes():
     assert _st(10, 4, G, method="nfft", window_m=1) == ks.KSUM_EINVAL
     assert _st(10, 4, G, method="nfft", n_coeff=128, T=0.02) == ks.KSUM_OK
     assert _st(3072, 512, L) == ks.KSUM_OK
+    assert _st(10, 4, G, check_finite=1) == ks.KSUM_OK
+    assert _st(10, 4, N, check_finite=2) == ks.KSUM_EINVAL
+    assert _st(10, 4, G, check_finite=-1) == ks.KSUM_EINVAL
     assert ks.ksum_last_error() != ""
 
 
