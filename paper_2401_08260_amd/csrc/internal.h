@@ -129,7 +129,7 @@ struct Layout {
   size_t off_wpart = 0;          // double[kWsumBlocks]
   size_t off_params = 0;         // SliceParams[B]
   size_t off_bounds = 0;         // uint32[B][2]
-  size_t off_counter = 0;        // uint32 tile queue of the projection
+  size_t off_counter = 0;        // uint32[16] tile queue heads of the projection
   size_t off_bounds_part = 0;    // uint32[blocks][B][2] per-block min / max of the projection
   size_t off_z = 0;              // float[B][L]
   size_t off_t1 = 0;             // float[B][M]

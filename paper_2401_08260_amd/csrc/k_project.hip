@@ -222,8 +222,9 @@ __global__ __launch_bounds__(256) void proj_gemm_kernel(GemmCtl g, PointLoader<I
   }
 }
 
+// clears the tile queue heads (one per XCD for the split-BF16 kernel, the first for FP32)
 __global__ void gemm_init_kernel(uint32_t *counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+  if (threadIdx.x < 16 && blockIdx.x == 0) counter[threadIdx.x] = 0u;
 }
 
 int projection_blocks(const ksum_plan &plan, int64_t L, int nsl) {

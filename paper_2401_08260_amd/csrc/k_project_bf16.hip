@@ -9,13 +9,23 @@
 // product at a sixteenth of the FP32 MFMA cycles per product.
 //
 // The directions are split once when the plan is made; the points are split as
-// their tile is moved from registers to LDS.  A workgroup computes 128 slices x
-// 256 points (4 waves, 2 x 2, each 64 slices x 128 points = 2 x 4 MFMA blocks),
-// K step 16 double buffered in LDS.  An LDS row holds the 16 hi values of the step
-// (32 B), then the 16 lo values (32 B), padded to 80 B so that the 16-byte fragment
-// reads of 8 neighbouring rows fall on distinct banks.  Lane l of an MFMA supplies
-// row l % 32 and the 8 contraction indices 8 (l / 32) .. + 7 of the step for both
-// operands.
+// their tile moves from registers to LDS.  A workgroup of 8 waves computes 256
+// slices x 256 points (waves 4 x 2, each 64 slices x 128 points = 2 x 4 MFMA
+// blocks), one block per CU and so two waves per SIMD.  The K loop runs in steps
+// of 32 (two MFMA contraction steps of 16, 48 MFMAs per wave between barriers)
+// through two LDS stages: the global loads of step k + 1 are issued before step k
+// is computed and go to the other stage after it, behind one barrier per step.  An
+// LDS row holds the 32 hi values of the step (64 B), then the 32 lo values (64 B),
+// padded to 144 B so that the 16-byte fragment reads of 8 neighbouring rows fall
+// on distinct banks.  Lane l of an MFMA supplies row l % 32 and the 8 contraction
+// indices 8 (l / 32) .. + 7 of its contraction step for both operands.
+//
+// Work items are (slice tile, point tile) pairs in slice-tile-major order, cut
+// into 8 contiguous ranges, one per XCD (blocks are dispatched round-robin over
+// the XCDs, so block b runs on XCD b % 8); the blocks of an XCD take the items of
+// its range from their own counter.  An XCD so works on one slice tile at a time,
+// whose directions (hi + lo) stay in its L2 while the point tiles stream past, and
+// the XCDs that share a slice tile stream their point tiles in the same order.
 #include <algorithm>
 
 #include "project_common.h"
@@ -28,16 +38,18 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-constexpr int SM = 128;          // slices per tile
+constexpr int NT = 512;          // threads per block
+constexpr int SM = 256;          // slices per tile
 constexpr int SN = 256;          // points per tile
-constexpr int SK = kGemmBK;      // 16
-constexpr int ROWB = 80;         // bytes per LDS row (32 hi + 32 lo + 16 pad)
+constexpr int SK = 2 * kGemmBK;  // 32 (the plan pads d to it)
+constexpr int ROWB = 144;        // bytes per LDS row (64 hi + 64 lo + 16 pad)
 constexpr int A_BYTES = SM * ROWB;
 constexpr int B_BYTES = SN * ROWB;
-constexpr int STAGE_BYTES = A_BYTES + B_BYTES;   // 30 KB
-constexpr int LDC = SN + 4;      // floats per row of the staged output (32 rows at a time)
+constexpr int STAGE_BYTES = A_BYTES + B_BYTES;   // 72 KB
+constexpr int NSTAGE = 2;
+constexpr int XCDS = 8;
 
-static_assert(32 * LDC * 4 <= 2 * STAGE_BYTES, "output staging must fit the stage buffers");
+static_assert(kGemmBM * 2 == SM, "the plan pads P to whole tiles of this kernel");
 
 // hi / lo halves of 4 consecutive FP32 values, packed as 4 bf16 each
 __device__ __forceinline__ void split4(const float4 v, uint2 &hi, uint2 &lo) {
@@ -49,38 +61,93 @@ __device__ __forceinline__ void split4(const float4 v, uint2 &hi, uint2 &lo) {
   lo = make_uint2(__builtin_bit_cast(uint32_t, l0), __builtin_bit_cast(uint32_t, l1));
 }
 
+// 4 consecutive values of a point row from column k (zero at and beyond d for VW < 4).
+// The 16-byte path (VW = 4, d % 4 == 0) loads from a column clamped into the row; the
+// values past d are set to zero when the step is stored (zero_tail), not here, so
+// that nothing waits for the load before it is needed.  Rows beyond the union were
+// pointed at a valid row by the caller (their products go to columns that are never
+// stored).
+template <typename InT, int VW>
+__device__ __forceinline__ float4 row4(const InT *src, int k, int d) {
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if constexpr (VW == 4) {
+    v = *reinterpret_cast<const float4 *>(src + min(k, d - 4));
+  } else if constexpr (VW == 2) {
+    if (k < d) {
+      const float2 q = *reinterpret_cast<const float2 *>(src + k);
+      v.x = q.x;
+      v.y = q.y;
+    }
+    if (k + 2 < d) {
+      const float2 q = *reinterpret_cast<const float2 *>(src + k + 2);
+      v.z = q.x;
+      v.w = q.y;
+    }
+  } else {
+    if (k + 0 < d) v.x = (float)src[k + 0];
+    if (k + 1 < d) v.y = (float)src[k + 1];
+    if (k + 2 < d) v.z = (float)src[k + 2];
+    if (k + 3 < d) v.w = (float)src[k + 3];
+  }
+  return v;
+}
+
+__device__ __forceinline__ float4 zero_tail(float4 v, bool in) {
+  return make_float4(in ? v.x : 0.f, in ? v.y : 0.f, in ? v.z : 0.f, in ? v.w : 0.f);
+}
+
+// The global data of one K step held by a thread between its load and its LDS store:
+// 16 hi and 16 lo direction values of one row, and 4 x 4 point values.
+struct StepRegs {
+  uint4 ah0, ah1, al0, al1;
+  float4 b[4];
+};
+
 }  // namespace
 
 template <typename InT, int VW>
-__global__ __launch_bounds__(256, 2) void proj_gemm_bf16x3_kernel(GemmCtl g, PointLoader<InT, VW> ld) {
-  __shared__ __align__(16) char smem[2 * STAGE_BYTES];
+__global__ __launch_bounds__(NT, 1) void proj_gemm_bf16x3_kernel(GemmCtl g, PointLoader<InT, VW> ld) {
+  __shared__ __align__(16) char smem[NSTAGE * STAGE_BYTES];
   __shared__ uint32_t smin[kMaxBatch], smax[kMaxBatch];
-  __shared__ int s_tile;
+  __shared__ int s_item;
 
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  const int wm = wid >> 1, wn = wid & 1;
+  const int wm = wid >> 1, wn = wid & 1;    // 64-slice rows wm, 128-point columns wn
   const int lr = lane & 31, lh = lane >> 5;
-  for (int i = t; i < g.nsl; i += 256) {
+  for (int i = t; i < g.nsl; i += NT) {
     smin[i] = 0xffffffffu;
     smax[i] = 0u;
   }
-  const int total = g.n_col_tiles * g.n_row_tiles;
+  const int64_t total = (int64_t)g.n_col_tiles * g.n_row_tiles;
+  const int xcd = blockIdx.x % XCDS;
+  const int64_t lo = total * xcd / XCDS, hi = total * (xcd + 1) / XCDS;
   const int nk = g.d_pad / SK;
-  auto As = [&](int b) { return smem + b * STAGE_BYTES; };
-  auto Bs = [&](int b) { return smem + b * STAGE_BYTES + A_BYTES; };
-  // direction tile: thread t moves 8 hi and 8 lo values of row t / 2
-  const int arow = t >> 1, akh = (t & 1) * 8;
+  const int d = ld.d;
+  auto As = [&](int s) { return smem + s * STAGE_BYTES; };
+  auto Bs = [&](int s) { return smem + s * STAGE_BYTES + A_BYTES; };
+  // direction tile: thread t moves 16 hi and 16 lo values of row t / 2; point tile:
+  // columns k4 .. k4 + 3 of rows t / 8 + 64 q, q = 0..3
+  const int arow = t >> 1, akh = (t & 1) * 16;
+  const int brow = t >> 3, k4 = (t & 7) * 4;
 
   while (true) {
-    if (t == 0) s_tile = (int)atomicAdd(g.counter, 1u);
+    if (t == 0) s_item = (int)(lo + (int64_t)atomicAdd(g.counter + xcd, 1u));
     __syncthreads();
-    const int tile = s_tile;
-    if (tile >= total) break;
-    const int col_tile = tile / g.n_row_tiles;
-    const int row_tile = tile % g.n_row_tiles;
-    const int64_t l0 = (int64_t)col_tile * SN;
+    const int64_t item = s_item;
+    if (item >= hi) break;
+    const int row_tile = (int)(item / g.n_col_tiles);
+    const int64_t col_tile = item % g.n_col_tiles;
+    const int64_t l0 = col_tile * SN;
     const int r0 = row_tile * SM;
     const int64_t aoff = (int64_t)(g.p0 + r0 + arow) * g.d_pad + akh;
+    const uint16_t *ahp = g.dirs_hi + aoff;
+    const uint16_t *alp = g.dirs_lo + aoff;
+    const InT *bsrc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t l = l0 + brow + 64 * q;    // rows beyond the union read row 0 of y
+      bsrc[q] = (l >= ld.L) ? ld.y : (l < ld.M) ? ld.y + l * (int64_t)d : ld.x + (l - ld.M) * (int64_t)d;
+    }
 
     f32x16 acc[2][4];
 #pragma unroll
@@ -90,144 +157,122 @@ __global__ __launch_bounds__(256, 2) void proj_gemm_bf16x3_kernel(GemmCtl g, Poi
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    auto store_a = [&](char *S, uint4 hi, uint4 lo) {
-      *reinterpret_cast<uint4 *>(S + arow * ROWB + akh * 2) = hi;
-      *reinterpret_cast<uint4 *>(S + arow * ROWB + 32 + akh * 2) = lo;
+    // steps past the end load the last step again (in bounds, never stored)
+    auto load_step = [&](int kb) {
+      const int k0 = min(kb, nk - 1) * SK;
+      StepRegs R;
+      R.ah0 = *reinterpret_cast<const uint4 *>(ahp + k0);
+      R.ah1 = *reinterpret_cast<const uint4 *>(ahp + k0 + 8);
+      R.al0 = *reinterpret_cast<const uint4 *>(alp + k0);
+      R.al1 = *reinterpret_cast<const uint4 *>(alp + k0 + 8);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) R.b[q] = row4<InT, VW>(bsrc[q], k0 + k4, d);
+      return R;
     };
-    auto store_b = [&](char *S, int e, float4 v) {
-      const int row = e >> 2, k4 = (e & 3) * 4;
-      uint2 hi, lo;
-      split4(v, hi, lo);
-      *reinterpret_cast<uint2 *>(S + row * ROWB + k4 * 2) = hi;
-      *reinterpret_cast<uint2 *>(S + row * ROWB + 32 + k4 * 2) = lo;
+    auto store_step = [&](int s, int kb, const StepRegs &R) {
+      char *A = As(s) + arow * ROWB + akh * 2;
+      *reinterpret_cast<uint4 *>(A) = R.ah0;
+      *reinterpret_cast<uint4 *>(A + 16) = R.ah1;
+      *reinterpret_cast<uint4 *>(A + 64) = R.al0;
+      *reinterpret_cast<uint4 *>(A + 80) = R.al1;
+      const bool in = VW < 4 || kb * SK + k4 < d;
+      char *B = Bs(s) + k4 * 2;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint2 bh, bl;
+        split4(zero_tail(R.b[q], in), bh, bl);
+        char *p = B + (brow + 64 * q) * ROWB;
+        *reinterpret_cast<uint2 *>(p) = bh;
+        *reinterpret_cast<uint2 *>(p + 64) = bl;
+      }
     };
-
-    uint4 ah = *reinterpret_cast<const uint4 *>(g.dirs_hi + aoff);
-    uint4 al = *reinterpret_cast<const uint4 *>(g.dirs_lo + aoff);
-    float4 b0 = ld.load1(l0, 0, t), b1 = ld.load1(l0, 0, t + 256);
-    float4 b2 = ld.load1(l0, 0, t + 512), b3 = ld.load1(l0, 0, t + 768);
-    store_a(As(0), ah, al);
-    store_b(Bs(0), t, b0);
-    store_b(Bs(0), t + 256, b1);
-    store_b(Bs(0), t + 512, b2);
-    store_b(Bs(0), t + 768, b3);
-    __syncthreads();
-
-    for (int kb = 0; kb < nk; ++kb) {
-      const int cur = kb & 1;
-      const bool more = kb + 1 < nk;
-      if (more) {
-        const int k0 = (kb + 1) * SK;
-        ah = *reinterpret_cast<const uint4 *>(g.dirs_hi + aoff + k0);
-        al = *reinterpret_cast<const uint4 *>(g.dirs_lo + aoff + k0);
-        b0 = ld.load1(l0, k0, t);
-        b1 = ld.load1(l0, k0, t + 256);
-        b2 = ld.load1(l0, k0, t + 512);
-        b3 = ld.load1(l0, k0, t + 768);
-      }
-      const char *pa = As(cur) + (wm * 64 + lr) * ROWB + lh * 16;
-      const char *pb = Bs(cur) + (wn * 128 + lr) * ROWB + lh * 16;
-      bf16x8 fa_hi[2], fa_lo[2], fb_hi[4], fb_lo[4];
+    auto compute = [&](int s) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        fa_hi[i] = *reinterpret_cast<const bf16x8 *>(pa + i * 32 * ROWB);
-        fa_lo[i] = *reinterpret_cast<const bf16x8 *>(pa + i * 32 * ROWB + 32);
-      }
+      for (int sub = 0; sub < 2; ++sub) {
+        const char *pa = As(s) + (wm * 64 + lr) * ROWB + sub * 32 + lh * 16;
+        const char *pb = Bs(s) + (wn * 128 + lr) * ROWB + sub * 32 + lh * 16;
+        bf16x8 fa_hi[2], fa_lo[2];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        fb_hi[j] = *reinterpret_cast<const bf16x8 *>(pb + j * 32 * ROWB);
-        fb_lo[j] = *reinterpret_cast<const bf16x8 *>(pb + j * 32 * ROWB + 32);
-      }
-      // small terms first, then hi x hi
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i) {
+          fa_hi[i] = *reinterpret_cast<const bf16x8 *>(pa + i * 32 * ROWB);
+          fa_lo[i] = *reinterpret_cast<const bf16x8 *>(pa + i * 32 * ROWB + 64);
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa_lo[i], fb_hi[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa_hi[i], fb_lo[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa_hi[i], fb_hi[j], acc[i][j], 0, 0, 0);
+          const bf16x8 fb_hi = *reinterpret_cast<const bf16x8 *>(pb + j * 32 * ROWB);
+          const bf16x8 fb_lo = *reinterpret_cast<const bf16x8 *>(pb + j * 32 * ROWB + 64);
+          // small terms first, then hi x hi
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa_lo[i], fb_hi, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa_hi[i], fb_lo, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa_hi[i], fb_hi, acc[i][j], 0, 0, 0);
+          }
         }
-      if (more) {
-        store_a(As(cur ^ 1), ah, al);
-        store_b(Bs(cur ^ 1), t, b0);
-        store_b(Bs(cur ^ 1), t + 256, b1);
-        store_b(Bs(cur ^ 1), t + 512, b2);
-        store_b(Bs(cur ^ 1), t + 768, b3);
       }
+    };
+
+    // step kb: the loads of kb + 1 go out first, kb is computed from its stage, then
+    // kb + 1 goes to the other stage (read during step kb - 1, before the last barrier)
+    store_step(0, 0, load_step(0));
+    __syncthreads();
+    int s0 = 0;
+    for (int kb = 0; kb < nk; ++kb) {
+      const StepRegs R = load_step(kb + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(s0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (kb + 1 < nk) store_step(s0 ^ 1, kb + 1, R);
       __syncthreads();
+      s0 ^= 1;
     }
 
-    // Epilogue in four passes of 32 slices (h = slice half, i = MFMA row block): the
-    // waves holding the rows stage them in LDS, then every thread takes 32 values of
-    // one row (8 float4 at a stride of 32 columns: 8 neighbouring threads cover 128
-    // contiguous bytes per store), writes them to Z and folds them into the row's
-    // min / max.
-    float *C = reinterpret_cast<float *>(smem);
+    // Epilogue straight from the accumulators: element r of block (i, j) of a lane is
+    // slice row wm * 64 + 32 i + 8 (r / 4) + 4 lh + r % 4 and point column
+    // wn * 128 + 32 j + lr, so one store instruction covers two rows of 32 consecutive
+    // points (two 128-byte runs).  Row minima / maxima: over the lane's 4 point blocks,
+    // then over the 32 lanes of the row, then into LDS.
+    const int64_t cbase = l0 + wn * 128 + lr;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int i = 0; i < 2; ++i) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        if (wm == h) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-              C[(8 * (r >> 2) + 4 * lh + (r & 3)) * LDC + wn * 128 + j * 32 + lr] = acc[i][j][r];
-        }
-        __syncthreads();
-        const int lrow = t >> 3;                           // row within the 32
-        const int row = r0 + h * 64 + i * 32 + lrow;       // slice within the batch
-        const int c0 = (t & 7) * 4;
+      for (int r = 0; r < 16; ++r) {
+        const int row = r0 + wm * 64 + 32 * i + 8 * (r >> 2) + 4 * lh + (r & 3);
         float vmin = __builtin_huge_valf(), vmax = -__builtin_huge_valf();
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const int c = c0 + 32 * k;
-          const float4 v = *reinterpret_cast<const float4 *>(C + lrow * LDC + c);
-          const int64_t l = l0 + c;
-          if (row < g.nsl) {
-            float *dst = g.Z + (int64_t)row * g.ldz + l;
-            if (g.z_vec4 && l + 3 < ld.L) {
-              store_z4(dst, v);
-            } else {
-              if (l + 0 < ld.L) dst[0] = v.x;
-              if (l + 1 < ld.L) dst[1] = v.y;
-              if (l + 2 < ld.L) dst[2] = v.z;
-              if (l + 3 < ld.L) dst[3] = v.w;
-            }
-          }
-          if (l + 3 < ld.L) {
-            vmin = fminf(vmin, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
-            vmax = fmaxf(vmax, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
-          } else {
-            if (l + 0 < ld.L) { vmin = fminf(vmin, v.x); vmax = fmaxf(vmax, v.x); }
-            if (l + 1 < ld.L) { vmin = fminf(vmin, v.y); vmax = fmaxf(vmax, v.y); }
-            if (l + 2 < ld.L) { vmin = fminf(vmin, v.z); vmax = fmaxf(vmax, v.z); }
+        for (int j = 0; j < 4; ++j) {
+          const int64_t l = cbase + 32 * j;
+          const float v = acc[i][j][r];
+          if (l < ld.L) {
+            if (row < g.nsl) __builtin_nontemporal_store(v, g.Z + (int64_t)row * g.ldz + l);
+            vmin = fminf(vmin, v);
+            vmax = fmaxf(vmax, v);
           }
         }
 #pragma unroll
-        for (int off = 1; off < 8; off <<= 1) {
+        for (int off = 1; off < 32; off <<= 1) {
           vmin = fminf(vmin, __shfl_xor(vmin, off, 64));
           vmax = fmaxf(vmax, __shfl_xor(vmax, off, 64));
         }
-        if ((t & 7) == 0 && row < g.nsl && vmin <= vmax) {
+        if (lr == 0 && row < g.nsl && vmin <= vmax) {
           atomicMin(&smin[row], float_key(vmin));
           atomicMax(&smax[row], float_key(vmax));
         }
-        __syncthreads();
       }
     }
   }
   __syncthreads();
   uint32_t *out = g.part + (int64_t)blockIdx.x * g.nsl * 2;
-  for (int i = t; i < g.nsl; i += 256) {
+  for (int i = t; i < g.nsl; i += NT) {
     out[2 * i] = smin[i];
     out[2 * i + 1] = smax[i];
   }
 }
 
+// One block per CU, a multiple of 8 blocks so that every XCD's range has blocks.
 int projection_bf16x3_blocks(int64_t L, int nsl) {
   const int64_t tiles = ((L + SN - 1) / SN) * (int64_t)((nsl + SM - 1) / SM);
-  return (int)std::min<int64_t>(tiles, 256 * kGemmBlocksPerCU);
+  return (int)std::min<int64_t>(xcd_grid(tiles), 256);
 }
 
 hipError_t launch_projection_bf16x3(const ExecArgs &a, GemmCtl g) {
@@ -241,16 +286,16 @@ hipError_t launch_projection_bf16x3(const ExecArgs &a, GemmCtl g) {
   const bool al8 = ((uintptr_t)a.x % 8 == 0) && ((uintptr_t)a.y % 8 == 0);
   if (a.f64in) {
     PointLoader<double, 1> ld{(const double *)a.x, (const double *)a.y, lay.N, lay.M, lay.L, d};
-    proj_gemm_bf16x3_kernel<double, 1><<<grid, 256, 0, a.stream>>>(g, ld);
+    proj_gemm_bf16x3_kernel<double, 1><<<grid, NT, 0, a.stream>>>(g, ld);
   } else if (d % 4 == 0 && al16) {
     PointLoader<float, 4> ld{(const float *)a.x, (const float *)a.y, lay.N, lay.M, lay.L, d};
-    proj_gemm_bf16x3_kernel<float, 4><<<grid, 256, 0, a.stream>>>(g, ld);
+    proj_gemm_bf16x3_kernel<float, 4><<<grid, NT, 0, a.stream>>>(g, ld);
   } else if (d % 2 == 0 && al8) {
     PointLoader<float, 2> ld{(const float *)a.x, (const float *)a.y, lay.N, lay.M, lay.L, d};
-    proj_gemm_bf16x3_kernel<float, 2><<<grid, 256, 0, a.stream>>>(g, ld);
+    proj_gemm_bf16x3_kernel<float, 2><<<grid, NT, 0, a.stream>>>(g, ld);
   } else {
     PointLoader<float, 1> ld{(const float *)a.x, (const float *)a.y, lay.N, lay.M, lay.L, d};
-    proj_gemm_bf16x3_kernel<float, 1><<<grid, 256, 0, a.stream>>>(g, ld);
+    proj_gemm_bf16x3_kernel<float, 1><<<grid, NT, 0, a.stream>>>(g, ld);
   }
   return hipGetLastError();
 }

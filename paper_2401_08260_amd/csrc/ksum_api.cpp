@@ -326,8 +326,11 @@ static ksum_status plan_host_setup(int32_t d, int32_t P, ksum_kernel kernel, con
   pl->params.directions = nullptr;
   pl->use_sort = (kernel == KSUM_NEGDIST || kernel == KSUM_LAPLACIAN);
   pl->use_fourier = (kernel != KSUM_NEGDIST);
-  pl->d_pad = (int32_t)((d + kGemmBK - 1) / kGemmBK * kGemmBK);
-  pl->P_pad = (int32_t)((P + kGemmBM - 1) / kGemmBM * kGemmBM + kGemmBM);
+  // the split-BF16 GEMM takes K steps of 2 kGemmBK
+  const int kstep = (p.precision == KSUM_SPLIT_BF16) ? 2 * kGemmBK : kGemmBK;
+  pl->d_pad = (int32_t)((d + kstep - 1) / kstep * kstep);
+  // padding rows of zeros: a GEMM tile of up to 2 kGemmBM slices may start at any slice below P
+  pl->P_pad = (int32_t)((P + kGemmBM - 1) / kGemmBM * kGemmBM + 2 * kGemmBM);
   pl->Pk = (int32_t)((P + kGemmBK - 1) / kGemmBK * kGemmBK);
   pl->cd = std::sqrt(M_PI) * std::exp(std::lgamma((d + 1) / 2.0) - std::lgamma(d / 2.0));
   pl->sort_const = (kernel == KSUM_LAPLACIAN) ? pl->cd / p.sigma : pl->cd;

@@ -62,7 +62,7 @@ struct GemmCtl {
   int d_pad, p0, nsl;
   float *Z;
   int64_t ldz;
-  uint32_t *counter;      // tile queue head (zeroed before the launch)
+  uint32_t *counter;      // tile queue heads, 16 (zeroed before the launch)
   uint32_t *part;         // [gridDim.x][nsl][2] per-block min / max keys
   int n_col_tiles, n_row_tiles;
   const uint16_t *dirs_hi, *dirs_lo;   // split-BF16 directions [P_pad][d_pad] (split path only)
