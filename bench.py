@@ -1,23 +1,27 @@
 #!/usr/bin/env python3
 """Throughput of the sliced fast kernel summation on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload negdist]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload laplace]
 
-A step is one complete ksum_execute (projection, per-slice set-up, 1-D sums,
-slice average) over the workload's inputs, which are resident in HBM before the
-timed region starts.  The metric is target points x slices per second,
-M * P / t_step.  Prints one JSON line on stdout (logs go to stderr).
+The metric is target points x slices per second, M * P / t_step, at a relative
+error of at most 1e-3 against the exact direct sum.  The slicing error falls like
+P^-1/2 (Sec. 4), so the workload's own slice count P does not reach 1e-3; the run
+first measures the error at P against the exact sum on a subsample of targets, then
+sets P* = P (E_P / 1e-3)^2 x 1.2 (whole batches of 1024 slices), and a step is one
+complete ksum_execute (projection, per-slice set-up, 1-D sums, slice average) over
+all P* slices with the inputs resident in HBM.  The headline is the mixed form
+(split-BF16 projection); the plain FP32 form runs the same P* beside it.  Prints
+one JSON line on stdout (logs go to stderr).
 
 Besides the headline number the line carries
   * p50 / p99 step latency,
+  * the error of both forms against the exact sum at P*, and at the workload's P,
   * "roofline": the kernel with the largest share of the step, timed with HIP
-    events on the library's stream during a second timed region, its
-    algorithmic work per launch over its average launch duration, against the
-    MI355X peak of the resource that bounds it,
-  * "cpu_baseline": the FP64 CPU oracle timed on this host on a bounded sample
-    of the same workload (the first Q slices), plus the GPU result's error
-    against the oracle on those slices and against the exact direct sum on a
-    subsample of targets.
+    events on the library's stream, its algorithmic work over its launch time,
+    against the MI355X peak of the resource that bounds it,
+  * "cpu_baseline": the FP64 CPU oracle, threads over slices, timed on this host
+    on a bounded sample of the workload (the first Q slices), with the GPU's
+    per-slice sums compared against it on those slices.
 """
 from __future__ import annotations
 
@@ -38,10 +42,13 @@ import workloads as wlm  # noqa: E402
 
 METRIC = "target-pts x slices/s at <=1e-3 rel err vs direct, mixed vs FP32; p50/p99 latency"
 UNIT = "target-pts x slices/s"
+GATE = 1e-3          # relative error against the exact sum the metric asks for
+GATE_BATCH = 1024    # slices per batch of the runs at P*
 
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_FP32_VALU_TFLOPS = 157.3
 
 
@@ -60,11 +67,13 @@ def plan_kwargs(wl, sigma, precision="fp32"):
     return kw
 
 
-def kernel_work(stage, wl, P):
-    """Algorithmic work of one launch of a stage: (bound, amount, unit, peak).
+def kernel_work(stage, wl, P, precision="fp32"):
+    """Algorithmic work of a stage over P slices: (bound, amount, unit, peak).
 
     Per-unit figures (per slice unless noted; L = N + M):
-      project       2 d flops per point-slice            -> 2 (N+M) d P flops   (FP32 MFMA)
+      project       FP32: 2 d flops per point-slice -> 2 (N+M) d P flops (FP32 MFMA);
+                    split-BF16: the three BF16 products hi.hi + hi.lo + lo.hi of each
+                    FP32 product -> 3 x 2 (N+M) d P flops (BF16 MFMA)
       sort_group    8 B (key, index) per entry + 4 B weight per source + 4 B t per target
       sort_hist     4 B projection per entry + 4 B weight per source
       sort_scatter  4 B projection read + 8 B (key, index) write per entry
@@ -73,10 +82,14 @@ def kernel_work(stage, wl, P):
       accumulate    4 B t per target-slice read
       backproject   2 P flops per output coordinate     -> 2 R P d flops per launch, R = M (grad_y)
                     or N (grad_x); counted as (N + M) P d, the mean of the two launches (MFMA FP32)
+    The amount over all launches of a step divided by their summed duration is the
+    achieved rate (the per-launch work times the launches over the same time).
     """
     N, M, d = wl.N, wl.M, wl.d
     L = N + M
     if stage == "project":
+        if precision == "split_bf16":
+            return "mfma", 6.0 * L * d * P / 1e12, "TFLOP/s", PEAK_BF16_MFMA_TFLOPS
         return "mfma", 2.0 * L * d * P / 1e12, "TFLOP/s", PEAK_FP32_MFMA_TFLOPS
     if stage == "backproject":
         return "mfma", 1.0 * L * d * P / 1e12, "TFLOP/s", PEAK_FP32_MFMA_TFLOPS
@@ -107,8 +120,18 @@ STAGE_KERNEL = {
     "ndft_forward": ("ndft_forward_kernel", "k_fourier.hip"),
     "accumulate": ("accumulate_kernel", "k_reduce.hip"),
 }
-WORKLOAD_TAG = {"negdist": "negdist_N1e5_d784_P256", "laplace": "laplace_N2e5_d3072_P512",
-                "gauss_nfft": "gauss_nfft_N1e6_d50_P256", "gauss_ndft": "gauss_ndft_N1e3_d10_P64"}
+PROJECT_BF16 = ("proj_gemm_bf16x3_kernel", "k_project_bf16.hip")
+
+
+def stage_kernel(stage, precision):
+    if stage == "project" and precision == "split_bf16":
+        return PROJECT_BF16
+    return STAGE_KERNEL.get(stage)
+
+
+def workload_tag(wl, P, precision):
+    """Name of a workload's profile summaries: workload, sizes, slice count and precision."""
+    return f"{wl.name}_N{wl.N}_d{wl.d}_P{P}_{precision}"
 
 
 def measure_stream_peak(dev, nbytes=1 << 30, reps=5):
@@ -143,124 +166,89 @@ def source_digest(fname):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, stage):
+def measured_traffic(tag, stage, precision, launches):
     """HBM bytes per launch of a stage's kernel from the committed FETCH_SIZE / WRITE_SIZE
-    summary (already scaled by the copy-kernel calibration), or None when there is no
-    summary or the kernel's source differs from the one the counters were taken with."""
-    if stage not in STAGE_KERNEL or workload not in WORKLOAD_TAG:
+    summary profiles/hbm_traffic_<tag>.md (already scaled by the copy-kernel calibration
+    and given per launch), or None when there is no summary or the kernel's source
+    differs from the one the counters were taken with."""
+    sk = stage_kernel(stage, precision)
+    if sk is None:
         return None
-    kname, src = STAGE_KERNEL[stage]
-    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{WORKLOAD_TAG[workload]}.md")
+    kname, src = sk
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{tag}.md")
     if not os.path.exists(path):
         return None
     rd = wr = None
     digest = None
     with open(path) as f:
         for line in f:
-            if line.startswith("| `" + kname):
+            if line.startswith("| `" + kname + "`"):
                 cols = [c.strip() for c in line.strip().strip("|").split("|")]
                 rd, wr = float(cols[3]), float(cols[4])
             elif line.startswith("- source-digest " + src + " "):
                 digest = line.split()[-1]
     if rd is None or digest != source_digest(src):
         return None
-    return {"read_GB": rd, "write_GB": wr, "total_GB": rd + wr,
-            "source": os.path.relpath(path, ROOT)}
+    return {"read_GB": rd, "write_GB": wr, "total_GB": rd + wr, "source": os.path.relpath(path, ROOT)}
 
 
-def cpu_baseline(wl, x, y, w, sigma, xi, s_gpu, t_gpu, budget_s, exact_targets, s_mixed=None):
-    """Oracle timing on a bounded sample + errors of the GPU result (oracle leg)."""
-    from oracle import direct, sliced
-
+def worker_threads():
+    """Threads for the CPU leg: the cores this process may run on, at most 16 (the host
+    share of one GPU)."""
     try:
-        from threadpoolctl import threadpool_info
-        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        blas_threads = os.cpu_count() or 1
-    method = "sort" if wl.kernel == "negdist" else wl.method
-    # size the sample from the marginal cost of a slice (the first call also pays for
-    # converting the points), then take as many slices as the budget allows
-    def run(q):
-        t0 = time.perf_counter()
-        sliced.sliced_sum(wl.kernel, x, y, w, xi[:q], sigma, method, wl.n_coeff, wl.T, return_slices=True)
-        return time.perf_counter() - t0
-    q1 = min(wl.P, 4)
-    t1 = run(1)
-    tq = run(q1) if q1 > 1 else t1
-    per = max((tq - t1) / max(q1 - 1, 1), tq / q1 * 0.25, 1e-4)
-    Q = int(max(1, min(wl.P, (budget_s - t1) / per)))
-    t0 = time.perf_counter()
-    _, ts = sliced.sliced_sum(wl.kernel, x, y, w, xi[:Q], sigma, method, wl.n_coeff, wl.T, return_slices=True)
-    dt = time.perf_counter() - t0
-    out = {"value": wl.M * Q / dt, "unit": UNIT, "cores": int(blas_threads), "kind": "oracle",
-           "sample": f"first {Q} of {wl.P} slices at full N={wl.N}, M={wl.M}, d={wl.d} "
-                     f"({dt:.1f} s; FP64 projection + per-slice 1-D fast sum)"}
-    # parity of the GPU per-slice sums on the sampled slices
-    if t_gpu is not None:
-        par = sliced.rel_l2(t_gpu[:Q].astype(np.float64), ts)
-    elif Q == wl.P:   # every slice was sampled: compare the averages
-        par = sliced.rel_l2(s_gpu.astype(np.float64), ts.mean(axis=0))
-    else:
-        par = None
-    # error of the GPU result against the exact sum on a subsample of targets (also timed)
-    k = min(exact_targets, wl.M)
-    t0 = time.perf_counter()
-    ex = direct.direct_sum(wl.kernel, x, y[:k], w, sigma if sigma > 0 else 1.0)
-    dte = time.perf_counter() - t0
-    s_sub = s_gpu[:k].astype(np.float64)
-    errs = {"parity_rel_l2_vs_oracle": par, "parity_slices": Q,
-            "exact_rel_l2": sliced.rel_l2(s_sub, ex),
-            "exact_per_summand": sliced.per_summand_error(s_sub, ex, w),
-            "exact_targets": k,
-            "direct_pairs_per_s": float(k) * wl.N / dte}
-    if s_mixed is not None:
-        sm = s_mixed[:k].astype(np.float64)
-        errs["mixed_exact_rel_l2"] = sliced.rel_l2(sm, ex)
-        errs["mixed_exact_per_summand"] = sliced.per_summand_error(sm, ex, w)
-    return out, errs, ex
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
-GATE = 1e-3    # relative error against the exact sum the metric asks for
+def cpu_baseline(wl, x64, y64, w, sigma, xi, t_gpu, budget_s, threads):
+    """The FP64 oracle on the first Q slices, threads over slices (each thread runs the
+    oracle's sliced sum on its own block of directions, BLAS single-threaded), and the
+    GPU's per-slice sums against it on those slices."""
+    from concurrent.futures import ThreadPoolExecutor
 
+    from threadpoolctl import threadpool_limits
 
-def error_gate(args, wl, sigma, xt, yt, wt, w_host, errs, exact):
-    """One run at P* slices, the count where the slicing error (rate P^-1/2) reaches the
-    gate, with the same directions extended (the first P are those of the main run).
-
-    The gate metric is the relative l2 error for non-negative weights and the paper's
-    per-summand error for signed weights.  P* = P (E / 1e-3)^2 x 1.2, rounded up to whole
-    batches of 1024 slices; both the FP32 and the split-BF16 projection are run and
-    their error is measured on the same exact targets as the main run."""
-    import torch
-    import paper_2401_08260_amd as ks
     from oracle import sliced
 
-    signed = bool(np.any(w_host < 0))
-    key = "exact_per_summand" if signed else "exact_rel_l2"
-    e0 = errs[key]
-    if e0 <= GATE:
-        return {"metric": key, "P": wl.P, "error_at_P": e0, "note": "gate met at the workload's P"}
-    Pstar = int(math.ceil(wl.P * (e0 / GATE) ** 2 * 1.2 / 1024.0)) * 1024
-    k = errs["exact_targets"]
-    out = {"metric": key, "error_at_P": e0, "P": Pstar, "slice_batch": 1024}
-    dev = xt.device
-    for prec in ("fp32", "split_bf16"):
-        plan = ks.Plan(wl.d, Pstar, wl.kernel, slice_batch=1024, **plan_kwargs(wl, sigma, prec))
-        s = torch.empty(wl.M, dtype=torch.float32, device=dev)
-        stream = torch.cuda.current_stream(dev)
-        e0v, e1v = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0v.record(stream)
-        plan(xt, yt, wt, out=s)
-        e1v.record(stream)
-        torch.cuda.synchronize()
-        ms = float(e0v.elapsed_time(e1v))
-        sub = s[:k].cpu().numpy().astype(np.float64)
-        err = sliced.per_summand_error(sub, exact, w_host) if signed else sliced.rel_l2(sub, exact)
-        out[prec] = {"ms": ms, "value": wl.M * Pstar / (ms * 1e-3), "error": err, "meets_gate": err <= GATE}
-        log(f"[bench] gate run P*={Pstar} {prec}: {ms:.1f} ms, {out[prec]['value']:.3e} {UNIT}, {key} {err:.2e}")
-        del plan
-    return out
+    method = "sort" if wl.kernel == "negdist" else wl.method
+
+    def block(q0, q1):
+        return sliced.sliced_sum(wl.kernel, x64, y64, w, xi[q0:q1], sigma, method, wl.n_coeff, wl.T,
+                                 return_slices=True)[1]
+
+    def run(Q):
+        nt = min(threads, Q)
+        cut = np.linspace(0, Q, nt + 1).astype(int)
+        with threadpool_limits(limits=1), ThreadPoolExecutor(max_workers=nt) as ex:
+            t0 = time.perf_counter()
+            parts = list(ex.map(lambda ab: block(*ab), zip(cut[:-1], cut[1:])))
+            dt = time.perf_counter() - t0
+        return np.concatenate(parts, axis=0), dt, nt
+
+    # one slice per thread sizes the sample, then as many rounds as the budget allows
+    q1 = min(threads, wl.P)
+    _, dt1, _ = run(q1)
+    rounds = max(1, int(budget_s / max(dt1, 1e-3)))
+    Q = int(min(wl.P, q1 * rounds))
+    ts, dt, nt = run(Q)
+    out = {"value": wl.M * Q / dt, "unit": UNIT, "cores": int(nt), "kind": "oracle",
+           "sample": f"first {Q} of {wl.P} slices at full N={wl.N}, M={wl.M}, d={wl.d}, {nt} threads over "
+                     f"slices ({dt:.1f} s; FP64 projection + per-slice 1-D sum as the oracle computes it)"}
+    tg = t_gpu[:Q].astype(np.float64)
+    par = {"parity_rel_l2_vs_oracle": sliced.rel_l2(tg, ts),
+           "parity_max_elementwise_vs_oracle": float(np.max(np.abs(tg - ts)) / np.max(np.abs(ts))),
+           "parity_slices": Q}
+    return out, par
+
+
+def exact_error(s, exact, w, signed):
+    """The gate metric: relative l2 error for non-negative weights, the paper's
+    per-summand error for signed weights (Sec. 4.1)."""
+    from oracle import sliced
+    sub = np.asarray(s[:exact.shape[0]], dtype=np.float64)
+    return sliced.per_summand_error(sub, exact, w) if signed else sliced.rel_l2(sub, exact)
 
 
 # ---------------------------------------------------------------------------
@@ -427,23 +415,96 @@ def bench_serve(args):
     print(json.dumps(result), flush=True)
 
 
+def timed_steps(step, K, W, stream):
+    """W untimed steps, then K steps bracketed by a synchronisation on both sides, with an
+    event after each step on the execution stream.  Returns (per-step ms, mean ms, wall s)."""
+    import torch
+    for _ in range(W):
+        step()
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    evs[0].record(stream)
+    for i in range(K):
+        step()
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(K)])
+    return per, float(evs[0].elapsed_time(evs[-1])) / K, wall
+
+
+def stage_breakdown(ks, plan, step, steps=1):
+    """Per-stage kernel time of `steps` steps with HIP events on the execution stream
+    (read back after every step): {stage: (ms per step, launches per step)}."""
+    import torch
+    ks.ksum_set_timing(plan.handle, True)
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        step()
+        st = ks.ksum_stage_times(plan.handle)
+    ks.ksum_set_timing(plan.handle, False)
+    return {k: (v[0] / steps, v[1] / steps) for k, v in st.items() if v[1] > 0}
+
+
+def roofline_of(stages, wl, P, precision, ms_step, tag):
+    """The stage with the largest share of the step among those with an algorithmic
+    work figure, against its roofline."""
+    dom = max((k for k in stages if kernel_work(k, wl, P, precision)), key=lambda k: stages[k][0])
+    bound, amount, unit, peak = kernel_work(dom, wl, P, precision)
+    ms, launches = stages[dom]
+    achieved = amount / (ms * 1e-3)
+    tr = measured_traffic(tag, dom, precision, launches)
+    return {"kernel": dom, "kernel_name": stage_kernel(dom, precision)[0], "bound": bound, "achieved": achieved,
+            "peak": peak, "unit": unit, "frac": achieved / peak,
+            "traffic": tr["total_GB"] if tr else None,
+            "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)", "traffic_detail": tr,
+            "avg_launch_ms": ms / launches, "launches_per_step": launches,
+            "work_per_launch": amount / launches, "share_of_step": ms / ms_step}
+
+
+def stage_rooflines(stages, wl, P, precision, tag, stream_gbps):
+    """Every stage with a work figure against its roofline; HBM-bound stages also with the
+    measured traffic of the committed counter summary where it matches the source."""
+    out = {}
+    for k, (ms, launches) in stages.items():
+        kw = kernel_work(k, wl, P, precision)
+        if not kw:
+            continue
+        b, amt, u, pk = kw
+        ach = amt / (ms * 1e-3)
+        ent = {"bound": b, "ms_per_step": ms, "launches_per_step": launches, "achieved": ach, "unit": u,
+               "frac_peak": ach / pk}
+        trk = measured_traffic(tag, k, precision, launches)
+        if b == "hbm" and trk:
+            gbs = trk["total_GB"] * launches / (ms * 1e-3)
+            ent.update(measured_GBps=gbs, frac_peak_measured=gbs / PEAK_HBM_GBS,
+                       frac_stream_measured=gbs / stream_gbps)
+        out[k] = ent
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="negdist", choices=sorted(wlm.WORKLOADS) + ["serve"])
-    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="laplace", choices=sorted(wlm.WORKLOADS) + ["serve"])
+    ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-hbm-gb", type=float, default=64.0)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in the CPU leg")
-    ap.add_argument("--exact-targets", type=int, default=500)
+    ap.add_argument("--exact-targets", type=int, default=2000)
+    ap.add_argument("--fp32-steps", type=int, default=3, help="timed steps of the plain FP32 form at P*")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the split-BF16 (mixed) leg")
-    ap.add_argument("--no-gate", action="store_true", help="skip the run at the slice count of the error gate")
+    ap.add_argument("--no-gate", action="store_true",
+                    help="time the workload's own P instead of P* (no exact sum; stage detail and profiles)")
+    ap.add_argument("--precision", default="split_bf16", choices=["split_bf16", "fp32"],
+                    help="form of the headline (the other is timed beside it)")
     ap.add_argument("--backward", action="store_true",
-                    help="also time one gradient step (grad_x, grad_y, grad_w for an upstream grad_s)")
+                    help="also time one gradient step (grad_x, grad_y, grad_w for an upstream grad_s) at P")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device (reference for the HBM traffic counters)")
     args = ap.parse_args()
@@ -477,164 +538,125 @@ def main():
     sigma = wlm.kernel_scale(wl, x, y)
     dev = torch.device("cuda:0")
     xt, yt, wt = (torch.from_numpy(a).to(dev) for a in (x, y, w))
-    plan = ks.Plan(wl.d, wl.P, wl.kernel, **plan_kwargs(wl, sigma))
-    s = torch.empty(wl.M, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev)
+    signed = bool(np.any(w < 0))
+    err_key = "per_summand" if signed else "rel_l2"
+    head, other = args.precision, ("fp32" if args.precision == "split_bf16" else "split_bf16")
 
-    def step():
-        plan(xt, yt, wt, out=s)
+    # the exact sum on the first targets (FP64, CPU): the error of every run below
+    exact = None
+    if not args.no_gate:
+        from oracle import direct
+        k = min(args.exact_targets, wl.M)
+        t0 = time.perf_counter()
+        exact = direct.direct_sum(wl.kernel, x, y[:k], w, sigma if sigma > 0 else 1.0)
+        dte = time.perf_counter() - t0
+        log(f"[bench] exact sum on {k} targets: {dte:.1f} s ({k * wl.N / dte:.3e} pairs/s)")
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+    # the workload's own P: one run per form (error at P, stage detail, the probe for the CPU leg)
+    at_P = {}
+    probe_t = None
+    for prec in (head, other):
+        plan = ks.Plan(wl.d, wl.P, wl.kernel, **plan_kwargs(wl, sigma, prec))
+        s = torch.empty(wl.M, dtype=torch.float32, device=dev)
+        per, ms, _ = timed_steps(lambda: plan(xt, yt, wt, out=s), max(1, min(args.steps, 5)), 1, stream)
+        ent = {"P": wl.P, "ms_per_step": ms, "value": wl.M * wl.P / (ms * 1e-3)}
+        if exact is not None:
+            ent["error"] = exact_error(s.cpu().numpy(), exact, w, signed)
+        if prec == "fp32" and not args.no_cpu_baseline:
+            probe_t = torch.empty((wl.P, wl.M), dtype=torch.float32, device=dev)
+            plan(xt, yt, wt, out=s, probe={"t": probe_t})
+            torch.cuda.synchronize()
+            probe_t = probe_t.cpu().numpy()
+            xi = plan.directions()
+        at_P[prec] = ent
+        log(f"[bench] P={wl.P} {prec}: {ms:.3f} ms, {ent['value']:.4e} {UNIT}"
+            + (f", {err_key} error {ent['error']:.3e}" if "error" in ent else ""))
+        del plan
 
-    # timed region 1: headline throughput and per-step latency
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    evs[0].record(stream)
-    for i in range(args.steps):
-        step()
-        evs[i + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall
-    per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
-    ms = float(evs[0].elapsed_time(evs[-1])) / args.steps
-    value = wl.M * wl.P / (ms * 1e-3)
-    log(f"[bench] {ms:.3f} ms/step ({wall / args.steps * 1e3:.3f} ms wall), {value:.4e} {UNIT}")
+    # P*: the slice count at which the slicing error reaches the gate
+    if args.no_gate:
+        Pstar, batch = wl.P, 0
+    else:
+        e_P = at_P["fp32"]["error"]
+        Pstar = wl.P if e_P <= GATE else int(math.ceil(wl.P * (e_P / GATE) ** 2 * 1.2 / GATE_BATCH)) * GATE_BATCH
+        batch = GATE_BATCH if Pstar > wl.P else 0
+    log(f"[bench] timed slice count P* = {Pstar}" + (f" (batches of {batch})" if batch else ""))
 
-    # timed region 2: per-kernel durations with HIP events on the execution stream
-    ks.ksum_set_timing(plan.handle, True)
-    torch.cuda.synchronize()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    stages = ks.ksum_stage_times(plan.handle)
-    ks.ksum_set_timing(plan.handle, False)
-    stage_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1] > 0}
-    stage_share = {k: v[0] / args.steps for k, v in stages.items() if v[1] > 0}
-    for k in sorted(stage_share, key=lambda q: -stage_share[q]):
-        log(f"[bench]   {k:14s} {stage_share[k]:8.4f} ms/step  ({stages[k][1] // args.steps} launches/step)")
-    dom = max((k for k in stage_share if kernel_work(k, wl, wl.P)), key=lambda k: stage_share[k])
-    bound, amount, unit, peak = kernel_work(dom, wl, wl.P)
-    achieved = amount / (stage_ms[dom] * 1e-3)
-    tr = measured_traffic(wl.name, dom)
-    roofline = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": tr["total_GB"] if tr else None,
-                "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "traffic_detail": tr, "avg_launch_ms": stage_ms[dom],
-                "share_of_step": stage_share[dom] / ms}
-
-    # every stage against its roofline: algorithmic bytes (or flops) per launch over the
-    # launch time, and for HBM-bound stages the measured HBM traffic over the same time,
-    # as fractions of the nominal peak and of the copy bandwidth measured here
+    forms = {}
     stream_pk = measure_stream_peak(dev)
-    stage_roofline = {}
-    for k in stage_share:
-        kw = kernel_work(k, wl, wl.P)
-        if not kw:
-            continue
-        b, amt, u, pk = kw
-        ach = amt / (stage_ms[k] * 1e-3)
-        ent = {"bound": b, "avg_launch_ms": stage_ms[k], "achieved": ach, "unit": u, "frac_peak": ach / pk}
-        trk = measured_traffic(wl.name, k)
-        if b == "hbm" and trk:
-            gbs = trk["total_GB"] / (stage_ms[k] * 1e-3)
-            ent.update(measured_GBps=gbs, frac_peak_measured=gbs / PEAK_HBM_GBS,
-                       frac_stream_measured=gbs / stream_pk["GBps"])
-        stage_roofline[k] = ent
+    for prec, K, W in ((head, args.steps, args.warmup), (other, max(1, min(args.fp32_steps, args.steps)), 1)):
+        plan = ks.Plan(wl.d, Pstar, wl.kernel, slice_batch=batch, **plan_kwargs(wl, sigma, prec))
+        s = torch.empty(wl.M, dtype=torch.float32, device=dev)
 
-    # timed region 3: the same step with the split-BF16 projection ("mixed")
-    mixed = None
-    s_mixed = None
-    if not args.no_mixed:
-        plan_m = ks.Plan(wl.d, wl.P, wl.kernel, **plan_kwargs(wl, sigma, "split_bf16"))
-        sm = torch.empty(wl.M, dtype=torch.float32, device=dev)
-        for _ in range(args.warmup):
-            plan_m(xt, yt, wt, out=sm)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.steps):
-            plan_m(xt, yt, wt, out=sm)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms_m = float(e0.elapsed_time(e1)) / args.steps
-        ks.ksum_set_timing(plan_m.handle, True)
-        plan_m(xt, yt, wt, out=sm)
-        torch.cuda.synchronize()
-        st_m = ks.ksum_stage_times(plan_m.handle)
-        ks.ksum_set_timing(plan_m.handle, False)
-        s_mixed = sm.cpu().numpy().astype(np.float64)
-        s_fp32 = s.cpu().numpy().astype(np.float64)
-        mixed = {"precision": "split_bf16", "ms_per_step": ms_m, "value": wl.M * wl.P / (ms_m * 1e-3),
-                 "speedup_vs_fp32": ms / ms_m, "project_ms": st_m["project"][0] if "project" in st_m else None,
-                 "rel_l2_vs_fp32_result": float(np.linalg.norm(s_mixed - s_fp32) / np.linalg.norm(s_fp32))}
-        log(f"[bench] mixed (split-BF16 projection): {ms_m:.3f} ms/step, {mixed['value']:.4e} {UNIT}, "
-            f"x{mixed['speedup_vs_fp32']:.2f} vs FP32")
+        def step():
+            plan(xt, yt, wt, out=s)
 
-    # timed region 4 (--backward): the gradients of an MMD gradient-flow step, grad_x, grad_y
-    # and grad_w of s for a seeded upstream grad_s, on the same inputs and plan
+        per, ms, wall = timed_steps(step, K, W, stream)
+        tag = workload_tag(wl, Pstar, prec)
+        stages = stage_breakdown(ks, plan, step, 1)
+        ent = {"precision": prec, "P": Pstar, "steps": K, "warmup": W, "ms_per_step": ms, "wall_s": wall,
+               "value": wl.M * Pstar / (ms * 1e-3), "p50_ms": float(np.percentile(per, 50)),
+               "p99_ms": float(np.percentile(per, 99)),
+               "stage_ms_per_step": {k: v[0] for k, v in stages.items()},
+               "roofline": roofline_of(stages, wl, Pstar, prec, ms, tag),
+               "stage_roofline": stage_rooflines(stages, wl, Pstar, prec, tag, stream_pk["GBps"]),
+               "profile_tag": tag}
+        if exact is not None:
+            ent["error"] = exact_error(s.cpu().numpy(), exact, w, signed)
+            ent["meets_gate"] = bool(ent["error"] <= GATE)
+        forms[prec] = ent
+        log(f"[bench] P*={Pstar} {prec}: {ms:.3f} ms/step over {K} steps ({wall / K * 1e3:.3f} ms wall), "
+            f"{ent['value']:.4e} {UNIT}" + (f", {err_key} error {ent['error']:.3e}" if "error" in ent else ""))
+        for kname in sorted(stages, key=lambda q: -stages[q][0]):
+            log(f"[bench]   {kname:14s} {stages[kname][0]:9.4f} ms/step  ({stages[kname][1]:.0f} launches/step)")
+        del plan
+
+    # (--backward) the gradients of an MMD gradient-flow step at the workload's P, FP32
     backward = None
     if args.backward:
+        plan = ks.Plan(wl.d, wl.P, wl.kernel, **plan_kwargs(wl, sigma, "fp32"))
         gs = torch.from_numpy(np.random.default_rng(7).standard_normal(wl.M).astype(np.float32)).to(dev)
-        for _ in range(args.warmup):
-            plan.backward(xt, yt, wt, gs)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.steps):
-            plan.backward(xt, yt, wt, gs)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms_b = float(e0.elapsed_time(e1)) / args.steps
-        ks.ksum_set_timing(plan.handle, True)
-        torch.cuda.synchronize()
-        for _ in range(args.steps):
-            plan.backward(xt, yt, wt, gs)
-        torch.cuda.synchronize()
-        st_b = ks.ksum_stage_times(plan.handle)
-        ks.ksum_set_timing(plan.handle, False)
-        share_b = {k: v[0] / args.steps for k, v in st_b.items() if v[1] > 0}
-        backward = {"what": "grad_x, grad_y and grad_w of s for an upstream grad_s",
-                    "ms_per_step": ms_b, "stage_ms_per_step": share_b}
-        if st_b.get("backproject", (0.0, 0))[1] > 0:
-            bms = st_b["backproject"][0] / st_b["backproject"][1]
+        per, ms_b, _ = timed_steps(lambda: plan.backward(xt, yt, wt, gs), args.steps, args.warmup, stream)
+        st_b = stage_breakdown(ks, plan, lambda: plan.backward(xt, yt, wt, gs), 1)
+        backward = {"what": "grad_x, grad_y and grad_w of s for an upstream grad_s, FP32, at the workload's P",
+                    "P": wl.P, "ms_per_step": ms_b, "stage_ms_per_step": {k: v[0] for k, v in st_b.items()}}
+        if "backproject" in st_b:
+            bms, bl = st_b["backproject"]
             b_bound, b_amt, b_unit, b_pk = kernel_work("backproject", wl, wl.P)
-            backward["backproject_roofline"] = {"bound": b_bound, "avg_launch_ms": bms,
+            backward["backproject_roofline"] = {"bound": b_bound, "avg_launch_ms": bms / bl,
                                                 "achieved": b_amt / (bms * 1e-3), "peak": b_pk, "unit": b_unit,
                                                 "frac": b_amt / (bms * 1e-3) / b_pk}
-        log(f"[bench] backward (grad_x, grad_y, grad_w): {ms_b:.3f} ms/step")
+        log(f"[bench] backward (grad_x, grad_y, grad_w) at P={wl.P}: {ms_b:.3f} ms/step")
+        del plan
 
+    hd = forms[head]
     result = {
-        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "p50_ms": float(np.percentile(per, 50)),
-        "p99_ms": float(np.percentile(per, 99)), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "metric": METRIC, "value": hd["value"], "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": hd["ms_per_step"], "p50_ms": hd["p50_ms"], "p99_ms": hd["p99_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16" if head == "split_bf16" else "f32", "data": "synthetic",
         "config": {"workload": wl.name, "kernel": wl.kernel, "method": "sort" if wl.kernel == "negdist"
-                   else wl.method, "N": wl.N, "M": wl.M, "d": wl.d, "P": wl.P, "precision": "fp32",
-                   "input": wl.dtype, "sigma": sigma},
-        "stage_ms_per_step": stage_share,
-        "roofline": roofline,
+                   else wl.method, "N": wl.N, "M": wl.M, "d": wl.d, "P": Pstar, "slice_batch": batch,
+                   "P_workload": wl.P, "precision": head, "input": wl.dtype, "sigma": sigma,
+                   "error_metric": err_key, "exact_targets": int(exact.shape[0]) if exact is not None else 0},
+        "error": hd.get("error"), "meets_gate": hd.get("meets_gate"),
+        "roofline": hd["roofline"],
+        "stage_ms_per_step": hd["stage_ms_per_step"],
+        "stage_roofline": hd["stage_roofline"],
+        "forms": forms,
+        "mixed_vs_fp32": forms["fp32"]["ms_per_step"] / forms["split_bf16"]["ms_per_step"],
+        "at_workload_P": at_P,
         "stream_peak": stream_pk,
-        "stage_roofline": stage_roofline,
-        "mixed": mixed,
     }
     if backward is not None:
         result["backward"] = backward
-
     if not args.no_cpu_baseline:
-        probe_t = torch.empty((wl.P, wl.M), dtype=torch.float32, device=dev)
-        plan(xt, yt, wt, out=s, probe={"t": probe_t})
-        torch.cuda.synchronize()
-        base, errs, exact = cpu_baseline(wl, x, y, w, sigma, plan.directions(), s.cpu().numpy(),
-                                  probe_t.cpu().numpy(), args.cpu_budget,
-                                  args.exact_targets, s_mixed)
+        x64, y64 = x.astype(np.float64), y.astype(np.float64)
+        base, par = cpu_baseline(wl, x64, y64, w, sigma, xi, probe_t, args.cpu_budget, worker_threads())
         result["cpu_baseline"] = base
-        result["errors"] = errs
-        log(f"[bench] cpu baseline {base['value']:.3e} {UNIT} ({base['sample']}); errors {errs}")
-        if not args.no_gate:
-            result["error_gate"] = error_gate(args, wl, sigma, xt, yt, wt, w, errs, exact)
+        result["parity_vs_oracle"] = par
+        log(f"[bench] cpu baseline {base['value']:.3e} {UNIT} ({base['sample']}); parity {par}")
     print(json.dumps(result), flush=True)
 
 
