@@ -182,7 +182,8 @@ def measured_traffic(tag, stage, precision, launches):
     digest = None
     with open(path) as f:
         for line in f:
-            if line.startswith("| `" + kname + "`"):
+            head = "| `" + kname
+            if line.startswith(head) and line[len(head):len(head) + 1] in ("`", "<"):
                 cols = [c.strip() for c in line.strip().strip("|").split("|")]
                 rd, wr = float(cols[3]), float(cols[4])
             elif line.startswith("- source-digest " + src + " "):
