@@ -267,17 +267,19 @@ def serve_params(kernel, sigma):
     return {}
 
 
-def bench_serve(args):
-    """Replays the serving stream twice on one GPU and reports latency and throughput:
+def serve_replay(n_requests, rate, slots, hbm_gb, saturated=True):
+    """Replays the first n_requests of the serving stream on one GPU and reports latency and
+    throughput:
       * served: the request server (continuous batching, `slots` concurrent streams,
         admission by HBM footprint) with the split-BF16 projection;
-      * baseline: one request at a time in arrival order, FP32, on one stream.
+      * baseline: one request at a time in arrival order, FP32, on one stream;
+    at the stream's arrival times and, if `saturated`, with every request queued at once.
     Point sets live in HBM: per dimension and distribution one pool of 5e5 sources and
     one of 5e5 targets, and each request takes a contiguous block of rows of each."""
     import torch
     import paper_2401_08260_amd as ks
 
-    reqs = wlm.serving_stream(args.serve_requests, args.serve_rate, seed=4)
+    reqs = wlm.serving_stream(n_requests, rate, seed=4)
     dev = torch.device("cuda:0")
     gen = torch.Generator(device=dev)
     gen.manual_seed(4)
@@ -316,7 +318,7 @@ def bench_serve(args):
     work = float(sum(r["M"] * r["P"] for r in reqs))
 
     # plans made before any clock starts (server: one tiny request per plan key)
-    srv = ks.Server(slots=args.serve_slots, hbm_bytes=int(args.serve_hbm_gb * (1 << 30)))
+    srv = ks.Server(slots=slots, hbm_bytes=int(hbm_gb * (1 << 30)))
     first_of = {}
     for k, r in enumerate(reqs):
         first_of.setdefault((r["kernel"], r["d"], r["P"], r["data"]), k)
@@ -336,15 +338,16 @@ def bench_serve(args):
         out.update(extra)
         return out
 
-    def run_served(scale):
-        """Continuous batching with the split-BF16 projection; arrivals scaled by `scale`
-        (0 = every request queued at once)."""
+    def run_served(scale, window=64):
+        """Continuous batching with the split-BF16 projection; arrivals scaled by `scale`.
+        scale = 0 saturates the server: requests go in as fast as it takes them, at most
+        `window` outstanding (their output buffers are allocated as they are submitted)."""
         lat, t_end_max, keep = [], 0.0, {}
         t0 = time.monotonic()
         i = pending = 0
         while i < len(reqs) or pending:
             now = time.monotonic() - t0
-            while i < len(reqs) and reqs[i]["arrival"] * scale <= now:
+            while i < len(reqs) and reqs[i]["arrival"] * scale <= now and (scale > 0 or pending < window):
                 x, y, w, g = inputs(i)
                 s, gr = outputs(i)
                 keep[i] = (s, gr)
@@ -362,7 +365,7 @@ def bench_serve(args):
             time.sleep(5e-5)
         st = srv.stats()
         return summary(lat, t_end_max - reqs[0]["arrival"] * scale,
-                       {"precision": "split_bf16", "slots": args.serve_slots,
+                       {"precision": "split_bf16", "slots": slots,
                         "arena_peak_gb": st["arena_peak"] / 2**30})
 
     def run_baseline(scale):
@@ -388,31 +391,44 @@ def bench_serve(args):
         return summary(lat, t_end - reqs[0]["arrival"] * scale, {"precision": "fp32", "slots": 1})
 
     served = run_served(1.0)
-    log(f"[serve] served at {args.serve_rate:g} req/s: p50 {served['p50_ms']:.2f} ms p99 {served['p99_ms']:.2f} ms, "
-        f"{served['value']:.3e} {UNIT} over {served['makespan_s']:.2f} s")
+    log(f"[serve] {len(reqs)} requests, served at {rate:g} req/s: p50 {served['p50_ms']:.2f} ms "
+        f"p99 {served['p99_ms']:.2f} ms, {served['value']:.3e} {UNIT} over {served['makespan_s']:.2f} s")
     base = run_baseline(1.0)
-    log(f"[serve] one at a time at {args.serve_rate:g} req/s: p50 {base['p50_ms']:.2f} ms "
+    log(f"[serve] one at a time at {rate:g} req/s: p50 {base['p50_ms']:.2f} ms "
         f"p99 {base['p99_ms']:.2f} ms, {base['value']:.3e} {UNIT} over {base['makespan_s']:.2f} s")
-    served_sat = run_served(0.0)
-    log(f"[serve] served, all queued at once: {served_sat['value']:.3e} {UNIT} over {served_sat['makespan_s']:.2f} s")
-    base_sat = run_baseline(0.0)
-    log(f"[serve] one at a time, all queued at once: {base_sat['value']:.3e} {UNIT} "
-        f"over {base_sat['makespan_s']:.2f} s")
+    out = {"requests": len(reqs), "rate_per_s": rate, "plans": len(first_of), "served": served,
+           "one_at_a_time_fp32": base, "p50_speedup": base["p50_ms"] / served["p50_ms"],
+           "p99_speedup": base["p99_ms"] / served["p99_ms"]}
+    if saturated:
+        served_sat = run_served(0.0)
+        log(f"[serve] served, saturated (64 outstanding): {served_sat['value']:.3e} {UNIT} "
+            f"over {served_sat['makespan_s']:.2f} s")
+        base_sat = run_baseline(0.0)
+        log(f"[serve] one at a time, back to back: {base_sat['value']:.3e} {UNIT} "
+            f"over {base_sat['makespan_s']:.2f} s")
+        out["saturated"] = {"served": served_sat, "one_at_a_time_fp32": base_sat,
+                            "throughput_speedup": served_sat["value"] / base_sat["value"]}
     srv.close()
+    del plans, pools
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_serve(args):
+    """`--workload serve`: the serving replay as its own bench line."""
+    r = serve_replay(args.serve_requests, args.serve_rate, args.serve_slots, args.serve_hbm_gb, saturated=True)
+    served = r["served"]
     result = {
-        "metric": METRIC, "value": served["value"], "unit": UNIT, "n_gpus": 1, "steps": len(reqs),
-        "warmup": len(first_of),
-        "ms_per_step": 1e3 * served["makespan_s"] / len(reqs), "p50_ms": served["p50_ms"], "p99_ms": served["p99_ms"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+split_bf16",
-        "data": "synthetic",
-        "config": {"workload": "serve", "requests": len(reqs), "rate_per_s": args.serve_rate, "seed": 4,
+        "metric": METRIC, "value": served["value"], "unit": UNIT, "n_gpus": 1, "steps": r["requests"],
+        "warmup": r["plans"],
+        "ms_per_step": 1e3 * served["makespan_s"] / r["requests"], "p50_ms": served["p50_ms"],
+        "p99_ms": served["p99_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+split_bf16", "data": "synthetic",
+        "config": {"workload": "serve", "requests": r["requests"], "rate_per_s": args.serve_rate, "seed": 4,
                    "N_M": "log-uniform [1e3, 5e5]", "d": list(SERVE_D), "P": [64, 256],
                    "kernels": ["gaussian", "laplacian", "negdist"], "grad_fraction": 0.3},
-        "served": served, "one_at_a_time_fp32": base,
-        "p50_speedup": base["p50_ms"] / served["p50_ms"], "p99_speedup": base["p99_ms"] / served["p99_ms"],
-        "saturated": {"served": served_sat, "one_at_a_time_fp32": base_sat,
-                      "throughput_speedup": served_sat["value"] / base_sat["value"]},
     }
+    result.update({k: v for k, v in r.items() if k not in ("requests", "rate_per_s", "plans")})
     print(json.dumps(result), flush=True)
 
 
@@ -496,6 +512,9 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-hbm-gb", type=float, default=64.0)
+    ap.add_argument("--serve-in-line", type=int, default=1000,
+                    help="requests of the serving stream replayed at its arrival rate for the line's `serving` "
+                         "field (0 = none)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in the CPU leg")
     ap.add_argument("--exact-targets", type=int, default=2000)
     ap.add_argument("--fp32-steps", type=int, default=3, help="timed steps of the plain FP32 form at P*")
@@ -652,6 +671,12 @@ def main():
     }
     if backward is not None:
         result["backward"] = backward
+    if args.serve_in_line > 0:
+        # free this workload's device memory before the serving pools are drawn
+        del xt, yt, wt
+        torch.cuda.empty_cache()
+        result["serving"] = serve_replay(args.serve_in_line, args.serve_rate, args.serve_slots, args.serve_hbm_gb,
+                                         saturated=False)
     if not args.no_cpu_baseline:
         x64, y64 = x.astype(np.float64), y.astype(np.float64)
         base, par = cpu_baseline(wl, x64, y64, w, sigma, xi, probe_t, args.cpu_budget, worker_threads())
