@@ -79,6 +79,8 @@ def kernel_work(stage, wl, P, precision="fp32"):
       sort_scatter  4 B projection read + 8 B (key, index) write per entry
       nfft_spread   4 B projection + 4 B weight per source
       nfft_interp   4 B projection read + 4 B t write per target
+      split_points  once per call, not per slice: 4 B read + 4 B (bf16 hi + lo) written per
+                    point coordinate -> 8 (N+M) d bytes (split-BF16 plans with P > 2048)
       accumulate    4 B t per target-slice read
       backproject   2 P flops per output coordinate     -> 2 R P d flops per launch, R = M (grad_y)
                     or N (grad_x); counted as (N + M) P d, the mean of the two launches (MFMA FP32)
@@ -93,6 +95,8 @@ def kernel_work(stage, wl, P, precision="fp32"):
         return "mfma", 2.0 * L * d * P / 1e12, "TFLOP/s", PEAK_FP32_MFMA_TFLOPS
     if stage == "backproject":
         return "mfma", 1.0 * L * d * P / 1e12, "TFLOP/s", PEAK_FP32_MFMA_TFLOPS
+    if stage == "split_points":
+        return "hbm", 8.0 * L * d / 1e9, "GB/s", PEAK_HBM_GBS
     gb = {
         "sort_group": (8.0 * L + 4.0 * N + 4.0 * M) * P,
         "sort_hist": (4.0 * L + 4.0 * N) * P,
@@ -119,13 +123,18 @@ STAGE_KERNEL = {
     "ndft_adjoint": ("ndft_adjoint_kernel", "k_fourier.hip"),
     "ndft_forward": ("ndft_forward_kernel", "k_fourier.hip"),
     "accumulate": ("accumulate_kernel", "k_reduce.hip"),
+    "split_points": ("split_points_kernel", "k_project_bf16.hip"),
 }
+# split-BF16 projection: split inside the GEMM, or (P > TILED_MIN_P) fed from the
+# once-per-call step-tiled split by direct LDS copies
 PROJECT_BF16 = ("proj_gemm_bf16x3_kernel", "k_project_bf16.hip")
+PROJECT_BF16_TILED = ("proj_gemm_bf16x3_dma_kernel", "k_project_bf16.hip")
+TILED_MIN_P = 2048
 
 
-def stage_kernel(stage, precision):
+def stage_kernel(stage, precision, P=0):
     if stage == "project" and precision == "split_bf16":
-        return PROJECT_BF16
+        return PROJECT_BF16_TILED if P > TILED_MIN_P else PROJECT_BF16
     return STAGE_KERNEL.get(stage)
 
 
@@ -166,12 +175,12 @@ def source_digest(fname):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(tag, stage, precision, launches):
+def measured_traffic(tag, stage, precision, launches, P=0):
     """HBM bytes per launch of a stage's kernel from the committed FETCH_SIZE / WRITE_SIZE
     summary profiles/hbm_traffic_<tag>.md (already scaled by the copy-kernel calibration
     and given per launch), or None when there is no summary or the kernel's source
     differs from the one the counters were taken with."""
-    sk = stage_kernel(stage, precision)
+    sk = stage_kernel(stage, precision, P)
     if sk is None:
         return None
     kname, src = sk
@@ -472,8 +481,8 @@ def roofline_of(stages, wl, P, precision, ms_step, tag):
     bound, amount, unit, peak = kernel_work(dom, wl, P, precision)
     ms, launches = stages[dom]
     achieved = amount / (ms * 1e-3)
-    tr = measured_traffic(tag, dom, precision, launches)
-    return {"kernel": dom, "kernel_name": stage_kernel(dom, precision)[0], "bound": bound, "achieved": achieved,
+    tr = measured_traffic(tag, dom, precision, launches, P)
+    return {"kernel": dom, "kernel_name": stage_kernel(dom, precision, P)[0], "bound": bound, "achieved": achieved,
             "peak": peak, "unit": unit, "frac": achieved / peak,
             "traffic": tr["total_GB"] if tr else None,
             "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)", "traffic_detail": tr,
@@ -493,7 +502,7 @@ def stage_rooflines(stages, wl, P, precision, tag, stream_gbps):
         ach = amt / (ms * 1e-3)
         ent = {"bound": b, "ms_per_step": ms, "launches_per_step": launches, "achieved": ach, "unit": u,
                "frac_peak": ach / pk}
-        trk = measured_traffic(tag, k, precision, launches)
+        trk = measured_traffic(tag, k, precision, launches, P)
         if b == "hbm" and trk:
             gbs = trk["total_GB"] * launches / (ms * 1e-3)
             ent.update(measured_GBps=gbs, frac_peak_measured=gbs / PEAK_HBM_GBS,

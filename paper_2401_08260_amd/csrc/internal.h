@@ -54,7 +54,7 @@ struct SliceParams {
 enum StageId {
   ST_MISC = 0, ST_PROJECT, ST_SETUP, ST_NDFT_ADJOINT, ST_NDFT_FORWARD, ST_NFFT_SPREAD, ST_NFFT_GRID,
   ST_NFFT_INTERP, ST_SORT_HIST, ST_SORT_SCAN, ST_SORT_SCATTER, ST_SORT_GROUP, ST_ACCUMULATE,
-  ST_SORT_FALLBACK, ST_BACKPROJ, ST_COUNT
+  ST_SORT_FALLBACK, ST_BACKPROJ, ST_SPLIT_POINTS, ST_COUNT
 };
 
 constexpr int kTimerEvents = 16384;   // timing marks held between two reads of the stage times
@@ -93,6 +93,7 @@ struct ksum_plan {
   float *d_dirs = nullptr;       // [P_pad][d_pad] FP32, zero padded
   uint16_t *d_dirs_hi = nullptr; // [P_pad][d_pad] bf16 hi half of the FP32 directions (split-BF16)
   uint16_t *d_dirs_lo = nullptr; // [P_pad][d_pad] bf16 lo half (split-BF16)
+  uint16_t *d_dirs_tiled = nullptr; // [d_pad / 16][P_pad][32] step-tiled hi / lo (split-BF16, P > 256)
   float *d_dirsT = nullptr;      // [d][Pk] FP32 transposed directions (backward), Pk = P rounded up to 16
   int32_t Pk = 0;
   float *d_deconv = nullptr;     // [K+1] 1 / (n phihat(k))^2 (NFFT)
@@ -150,13 +151,29 @@ struct Layout {
   size_t off_desc = 0;           // int4[B][sort_groups] group descriptors
   size_t off_fail = 0;           // uint32 count (+63 pad) and uint32[B][sort_groups] fallback list
   size_t off_flag = 0;           // uint32 non-finite input flag (opt-in check)
+  bool presplit = false;         // the union is split to bf16 hi / lo once per call (split_tiled plans)
+  int64_t split_rows = 0;        // L rounded up to whole 256-point tiles
+  size_t off_split = 0;          // step-tiled split points [d_pad / 16][split_rows][32] bf16
   size_t total = 0;
 };
 
 constexpr int kWsumBlocks = 64;
 
-// batch > 0 sets the slices per batch (at most the plan's own batch size) in place of the plan's
-Layout make_layout(const ksum_plan &plan, int64_t N, int64_t M, int32_t batch = 0);
+// Step-tiled split-BF16 operands (directions and pre-split points): per step of 16
+// contraction indices s and per row r, 64 bytes holding four 16-byte chunks, c = 0, 1
+// the hi values of indices 16 s + 8 c .. + 7 and c = 2, 3 the lo values, chunk c in
+// slot c ^ tile_swz(r).  A step of 256 consecutive rows is one contiguous 16 KB block.
+__host__ __device__ inline int tile_swz(int64_t r) { return (int)(((r >> 1) ^ (r >> 3)) & 3); }
+
+// Split-BF16 plans with more than 8 tiles of 256 slices keep step-tiled directions and
+// split the points once per call into the same layout.  The split pass costs about
+// as much as 8 slice tiles save by being fed by it.
+constexpr int kTiledMinP = 8 * 2 * kGemmBM + 1;
+inline bool split_tiled(const ksum_plan &pl) { return pl.params.precision == KSUM_SPLIT_BF16 && pl.P >= kTiledMinP; }
+
+// batch > 0 sets the slices per batch (at most the plan's own batch size) in place of the plan's;
+// allow_presplit = false leaves out the region of the once-per-call split of the points
+Layout make_layout(const ksum_plan &plan, int64_t N, int64_t M, int32_t batch = 0, bool allow_presplit = true);
 
 // ---------------------------------------------------------------------------
 // Launch wrappers (defined in the .hip files).  All take the batch's first
@@ -204,6 +221,7 @@ hipError_t launch_weight_prep(const ExecArgs &a, const double *w64);
 hipError_t launch_projection(const ExecArgs &a);
 struct GemmCtl;
 hipError_t launch_projection_bf16x3(const ExecArgs &a, GemmCtl g);
+hipError_t launch_split_points(const ExecArgs &a);
 int projection_bf16x3_blocks(int64_t L, int nsl);
 int projection_blocks(const ksum_plan &plan, int64_t L, int nsl);
 hipError_t launch_slice_setup(const ExecArgs &a);

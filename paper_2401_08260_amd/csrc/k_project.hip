@@ -250,6 +250,10 @@ hipError_t launch_projection(const ExecArgs &a) {
   g.z_vec4 = (lay.L % 4 == 0) ? 1 : 0;
   g.dirs_hi = pl.d_dirs_hi;
   g.dirs_lo = pl.d_dirs_lo;
+  g.dirs_t = pl.d_dirs_tiled;
+  g.pts_t = lay.presplit ? wsp<uint16_t>(a, lay.off_split) : nullptr;
+  g.a_rows = pl.P_pad;
+  g.b_rows = lay.split_rows;
   mark(a, ST_MISC);
   gemm_init_kernel<<<1, 64, 0, a.stream>>>(g.counter);
   mark(a, ST_PROJECT);

@@ -8,8 +8,10 @@
 // the residuals r) are about 2^-16 |a b|: the result is close to an FP32 dot
 // product at a sixteenth of the FP32 MFMA cycles per product.
 //
-// The directions are split once when the plan is made; the points are split as
-// their tile moves from registers to LDS.  A workgroup of 8 waves computes 256
+// The directions are split once when the plan is made.  Plans with more than 8 tiles
+// of 256 slices also split the points once per call (split_points_kernel), into a
+// step-tiled layout that the kernel at the end of this file copies straight into
+// LDS; otherwise the points are split as their tile moves from registers to LDS.  A workgroup of 8 waves computes 256
 // slices x 256 points (waves 4 x 2, each 64 slices x 128 points = 2 x 4 MFMA
 // blocks), one block per CU and so two waves per SIMD.  The K loop runs in steps
 // of 32 (two MFMA contraction steps of 16, 48 MFMAs per wave between barriers)
@@ -104,6 +106,41 @@ struct StepRegs {
 };
 
 }  // namespace
+
+// Splits the union's points once into the step-tiled layout (tile_swz): hi = bf16(u_l[k]),
+// lo = bf16(u_l[k] - hi) for rows l < rows and k < d_pad (zero for l >= L or k >= d).
+// Thread e takes 16 values (one step) of one row and writes their 64 bytes: 16
+// consecutive threads take 16 consecutive rows at one step and groups of 16 take
+// consecutive steps, so a wave reads 256 consecutive bytes of each of 16 rows and
+// writes 1 KB blocks.  rows is a multiple of 16.
+template <typename InT, int VW>
+__global__ __launch_bounds__(256) void split_points_kernel(const InT *x, const InT *y, int64_t M, int64_t L,
+                                                          int d, int nst, int64_t rows, uint16_t *out) {
+  const int64_t n = rows * nst;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t grp = e / (16 * nst);
+    const int rem = (int)(e - grp * 16 * nst);
+    const int64_t l = grp * 16 + (rem & 15);
+    const int s = rem >> 4;
+    const int k0 = s * 16;
+    const InT *src = (l < M) ? y + l * (int64_t)d : x + (l - M) * (int64_t)d;
+    uint2 h[4], lo[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + 4 * q;
+      // 4 values from column k (zero past d for VW < 4; VW = 4 means d % 4 == 0)
+      const float4 v = (l < L && k < d) ? row4<InT, VW>(src, k, d) : make_float4(0.f, 0.f, 0.f, 0.f);
+      split4(v, h[q], lo[q]);
+    }
+    const uint4 chunk[4] = {make_uint4(h[0].x, h[0].y, h[1].x, h[1].y), make_uint4(h[2].x, h[2].y, h[3].x, h[3].y),
+                            make_uint4(lo[0].x, lo[0].y, lo[1].x, lo[1].y),
+                            make_uint4(lo[2].x, lo[2].y, lo[3].x, lo[3].y)};
+    uint4 *dst = reinterpret_cast<uint4 *>(out + ((int64_t)s * rows + l) * 32);
+    const int sw = tile_swz(l);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dst[c ^ sw] = chunk[c];
+  }
+}
 
 template <typename InT, int VW>
 __global__ __launch_bounds__(NT, 1) void proj_gemm_bf16x3_kernel(GemmCtl g, PointLoader<InT, VW> ld) {
@@ -269,6 +306,185 @@ __global__ __launch_bounds__(NT, 1) void proj_gemm_bf16x3_kernel(GemmCtl g, Poin
   }
 }
 
+// ---------------------------------------------------------------------------
+// Step-tiled operands (pre-split points): a K step of a 256-row tile of either
+// operand is one contiguous 16 KB block in global memory, laid out as it is needed in
+// LDS, so it goes straight into LDS (global_load_lds_dwordx4: each lane's 16 bytes
+// land at the wave's LDS address + 16 x lane) without passing through registers;
+// every copy instruction moves 1 KB of consecutive bytes.  Steps of 16 contraction
+// indices, four LDS stages of 32 KB, copies issued three steps ahead; one barrier per
+// step, before which every wave waits only for its own copies of the step about to
+// be read.
+//
+// An LDS row is 64 bytes: 16-byte chunks c = 0, 1 (hi, k 0..7 and 8..15) and 2, 3
+// (lo), chunk c of global row r in slot c ^ tile_swz(r).  The fragment reads of 8 (or
+// 16) consecutive rows at one chunk then hit distinct bank groups whether the LDS
+// serves 128 or 256 bytes per cycle.
+//
+// The compiler is not told about these copies (they are written as inline asm):
+// it would otherwise wait for all of them before every LDS read.  The waits are
+// explicit vmcnt counts; every other memory operation of the K loop is an LDS read.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int DK = kGemmBK;             // contraction indices per step (16)
+constexpr int DROW = DK * 4;            // bytes per LDS row: 32 hi + 32 lo
+constexpr int DTILE = SM * DROW;        // 16 KB per operand tile
+constexpr int DSTAGE = 2 * DTILE;       // A tile, then B tile
+constexpr int DNS = 4;                  // stages
+static_assert(SM == SN, "one row layout for both operands");
+
+// The 4 copies of one step of one wave: A rows (2 x 16) and B rows (2 x 16).
+__device__ __forceinline__ void dma_step(const char *a0, const char *a1, const char *b0, const char *b1,
+                                         uint32_t la0, uint32_t la1, uint32_t lb0, uint32_t lb1) {
+  asm volatile(
+      "s_mov_b32 m0, %4\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off\n\t"
+      "s_mov_b32 m0, %5\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off\n\t"
+      "s_mov_b32 m0, %6\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %2, off\n\t"
+      "s_mov_b32 m0, %7\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %3, off"
+      :
+      : "v"(a0), "v"(a1), "v"(b0), "v"(b1), "s"(la0), "s"(la1), "s"(lb0), "s"(lb1)
+      : "memory", "m0");
+}
+
+// s_waitcnt with only the vector-memory count set (expcnt and lgkmcnt at their maxima)
+template <int N> __device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 16, "vmcnt field");
+  __builtin_amdgcn_s_waitcnt(N | (0x7 << 4) | (0xF << 8));
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(NT, 1) void proj_gemm_bf16x3_dma_kernel(GemmCtl g, int64_t L) {
+  __shared__ __align__(1024) char smem[DNS * DSTAGE];
+  __shared__ uint32_t smin[kMaxBatch], smax[kMaxBatch];
+  __shared__ int s_item;
+
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int lr = lane & 31, lh = lane >> 5;
+  const uint32_t wu = __builtin_amdgcn_readfirstlane(wid);
+  for (int i = t; i < g.nsl; i += NT) {
+    smin[i] = 0xffffffffu;
+    smax[i] = 0u;
+  }
+  const int64_t total = (int64_t)g.n_col_tiles * g.n_row_tiles;
+  const int xcd = blockIdx.x % XCDS;
+  const int64_t lo = total * xcd / XCDS, hi = total * (xcd + 1) / XCDS;
+  const int nk = g.d_pad / DK;
+  const uint32_t lds0 = (uint32_t)(uintptr_t)smem;
+  // fragment reads of the point tile: tile row R = wn * 128 + 32 j + lr is global row
+  // l0 + R with l0 a multiple of 256, and tile_swz only looks at bits 1..4, so the slot
+  // of its chunk c is c ^ tile_swz(lr)
+  const int fswb = tile_swz(lr);
+  const int offb_hi = lr * DROW + ((lh ^ fswb) << 4), offb_lo = lr * DROW + (((2 + lh) ^ fswb) << 4);
+
+  while (true) {
+    if (t == 0) s_item = (int)(lo + (int64_t)atomicAdd(g.counter + xcd, 1u));
+    __syncthreads();
+    const int64_t item = s_item;
+    if (item >= hi) break;
+    const int row_tile = (int)(item / g.n_col_tiles);
+    const int64_t col_tile = item % g.n_col_tiles;
+    const int64_t l0 = col_tile * SN;
+    const int r0 = row_tile * SM;
+    // the slice tile starts at global row p0 + r0, which need not be a multiple of 32
+    const int fswa = tile_swz(g.p0 + r0 + lr);
+    const int offa_hi = lr * DROW + ((lh ^ fswa) << 4), offa_lo = lr * DROW + (((2 + lh) ^ fswa) << 4);
+    // wave w copies bytes [2048 w, 2048 w + 2048) of the step's A and B blocks
+    const char *ca = reinterpret_cast<const char *>(g.dirs_t + (int64_t)(g.p0 + r0) * 32) + wid * 2048 + lane * 16;
+    const char *cb = reinterpret_cast<const char *>(g.pts_t + l0 * 32) + wid * 2048 + lane * 16;
+    const int64_t astep = g.a_rows * DROW, bstep = g.b_rows * DROW;   // bytes per step
+    auto issue = [&](int kb) {
+      const uint32_t la = lds0 + (uint32_t)((kb & (DNS - 1)) * DSTAGE) + wu * 2048;
+      const char *pa = ca + kb * astep, *pb = cb + kb * bstep;
+      dma_step(pa, pa + 1024, pb, pb + 1024, la, la + 1024, la + DTILE, la + DTILE + 1024);
+    };
+
+    f32x16 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+#pragma unroll
+    for (int s = 0; s < DNS - 1; ++s)
+      if (s < nk) issue(s);
+    for (int kb = 0; kb < nk; ++kb) {
+      // this wave's copies of step kb are done once at most those of the (up to two)
+      // later steps already issued are outstanding
+      const int later = min(DNS - 2, nk - 1 - kb);
+      if (later >= 2) wait_vm<8>();
+      else if (later == 1) wait_vm<4>();
+      else wait_vm<0>();
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+      // every wave is past step kb - 1, so its stage takes the copies of step kb + 3
+      if (kb + DNS - 1 < nk) issue(kb + DNS - 1);
+      const char *A = smem + (kb & (DNS - 1)) * DSTAGE;
+      const char *B = A + DTILE;
+      bf16x8 fa_hi[2], fa_lo[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const char *pa = A + (wm * 64 + i * 32) * DROW;
+        fa_hi[i] = *reinterpret_cast<const bf16x8 *>(pa + offa_hi);
+        fa_lo[i] = *reinterpret_cast<const bf16x8 *>(pa + offa_lo);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const char *pb = B + (wn * 128 + j * 32) * DROW;
+        const bf16x8 fb_hi = *reinterpret_cast<const bf16x8 *>(pb + offb_hi);
+        const bf16x8 fb_lo = *reinterpret_cast<const bf16x8 *>(pb + offb_lo);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa_lo[i], fb_hi, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa_hi[i], fb_lo, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa_hi[i], fb_hi, acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+
+    // epilogue as in the kernel above
+    const int64_t cbase = l0 + wn * 128 + lr;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = r0 + wm * 64 + 32 * i + 8 * (r >> 2) + 4 * lh + (r & 3);
+        float vmin = __builtin_huge_valf(), vmax = -__builtin_huge_valf();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t l = cbase + 32 * j;
+          const float v = acc[i][j][r];
+          if (l < L) {
+            if (row < g.nsl) __builtin_nontemporal_store(v, g.Z + (int64_t)row * g.ldz + l);
+            vmin = fminf(vmin, v);
+            vmax = fmaxf(vmax, v);
+          }
+        }
+#pragma unroll
+        for (int off = 1; off < 32; off <<= 1) {
+          vmin = fminf(vmin, __shfl_xor(vmin, off, 64));
+          vmax = fmaxf(vmax, __shfl_xor(vmax, off, 64));
+        }
+        if (lr == 0 && row < g.nsl && vmin <= vmax) {
+          atomicMin(&smin[row], float_key(vmin));
+          atomicMax(&smax[row], float_key(vmax));
+        }
+      }
+    }
+  }
+  __syncthreads();
+  uint32_t *out = g.part + (int64_t)blockIdx.x * g.nsl * 2;
+  for (int i = t; i < g.nsl; i += NT) {
+    out[2 * i] = smin[i];
+    out[2 * i + 1] = smax[i];
+  }
+}
+
 // One block per CU, a multiple of 8 blocks so that every XCD's range has blocks.
 int projection_bf16x3_blocks(int64_t L, int nsl) {
   const int64_t tiles = ((L + SN - 1) / SN) * (int64_t)((nsl + SM - 1) / SM);
@@ -284,7 +500,9 @@ hipError_t launch_projection_bf16x3(const ExecArgs &a, GemmCtl g) {
   const int d = pl.d;
   const bool al16 = ((uintptr_t)a.x % 16 == 0) && ((uintptr_t)a.y % 16 == 0);
   const bool al8 = ((uintptr_t)a.x % 8 == 0) && ((uintptr_t)a.y % 8 == 0);
-  if (a.f64in) {
+  if (g.pts_t) {
+    proj_gemm_bf16x3_dma_kernel<<<grid, NT, 0, a.stream>>>(g, lay.L);
+  } else if (a.f64in) {
     PointLoader<double, 1> ld{(const double *)a.x, (const double *)a.y, lay.N, lay.M, lay.L, d};
     proj_gemm_bf16x3_kernel<double, 1><<<grid, NT, 0, a.stream>>>(g, ld);
   } else if (d % 4 == 0 && al16) {
@@ -297,6 +515,32 @@ hipError_t launch_projection_bf16x3(const ExecArgs &a, GemmCtl g) {
     PointLoader<float, 1> ld{(const float *)a.x, (const float *)a.y, lay.N, lay.M, lay.L, d};
     proj_gemm_bf16x3_kernel<float, 1><<<grid, NT, 0, a.stream>>>(g, ld);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_split_points(const ExecArgs &a) {
+  const ksum_plan &pl = *a.plan;
+  const Layout &lay = *a.lay;
+  uint16_t *out = wsp<uint16_t>(a, lay.off_split);
+  const int nst = pl.d_pad / kGemmBK;
+  const int64_t n = lay.split_rows * nst;
+  const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 16384);
+  mark(a, ST_SPLIT_POINTS);
+  const int d = pl.d;
+  const bool al16 = ((uintptr_t)a.x % 16 == 0) && ((uintptr_t)a.y % 16 == 0);
+  const bool al8 = ((uintptr_t)a.x % 8 == 0) && ((uintptr_t)a.y % 8 == 0);
+  if (a.f64in)
+    split_points_kernel<double, 1><<<grid, 256, 0, a.stream>>>((const double *)a.x, (const double *)a.y, lay.M,
+                                                               lay.L, d, nst, lay.split_rows, out);
+  else if (d % 4 == 0 && al16)
+    split_points_kernel<float, 4><<<grid, 256, 0, a.stream>>>((const float *)a.x, (const float *)a.y, lay.M, lay.L, d,
+                                                              nst, lay.split_rows, out);
+  else if (d % 2 == 0 && al8)
+    split_points_kernel<float, 2><<<grid, 256, 0, a.stream>>>((const float *)a.x, (const float *)a.y, lay.M, lay.L, d,
+                                                              nst, lay.split_rows, out);
+  else
+    split_points_kernel<float, 1><<<grid, 256, 0, a.stream>>>((const float *)a.x, (const float *)a.y, lay.M, lay.L, d,
+                                                              nst, lay.split_rows, out);
   return hipGetLastError();
 }
 

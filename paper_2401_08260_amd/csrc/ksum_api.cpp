@@ -114,7 +114,7 @@ static ksum_status validate(int32_t d, int32_t P, ksum_kernel kernel, const ksum
   return KSUM_OK;
 }
 
-Layout make_layout(const ksum_plan &pl, int64_t N, int64_t M, int32_t batch) {
+Layout make_layout(const ksum_plan &pl, int64_t N, int64_t M, int32_t batch, bool allow_presplit) {
   Layout y;
   y.N = N;
   y.M = M;
@@ -172,6 +172,13 @@ Layout make_layout(const ksum_plan &pl, int64_t N, int64_t M, int32_t batch) {
     y.off_fail = take((64 + (size_t)B * y.sort_groups) * sizeof(uint32_t));
   }
   y.off_flag = take(64);
+  // split-BF16 plans with many slice tiles split the points once per call instead of
+  // once per tile and batch
+  y.presplit = allow_presplit && split_tiled(pl);
+  if (y.presplit) {
+    y.split_rows = (int64_t)align_up((size_t)y.L, 2 * kGemmBM);
+    y.off_split = take((size_t)y.split_rows * pl.d_pad * 2 * sizeof(uint16_t));
+  }
   y.total = o;
   return y;
 }
@@ -244,7 +251,7 @@ static void note_use(ksum_plan *pl, hipStream_t stream) {
 static void free_plan(ksum_plan *pl) {
   if (!pl) return;
   free_timer(pl);
-  void *tabs[] = {pl->d_dirs, pl->d_dirs_hi, pl->d_dirs_lo, pl->d_dirsT, pl->d_deconv, pl->d_twiddle,
+  void *tabs[] = {pl->d_dirs, pl->d_dirs_hi, pl->d_dirs_lo, pl->d_dirs_tiled, pl->d_dirsT, pl->d_deconv, pl->d_twiddle,
                   pl->d_costab};
   bool on_device = pl->n_use > 0;
   for (void *t : tabs) on_device |= t != nullptr;
@@ -427,6 +434,21 @@ ksum_status ksum_plan_create(int32_t d, int32_t P, ksum_kernel kernel, const ksu
     const size_t nb = hd.size() * sizeof(uint16_t);
     if (!up(&pl->d_dirs_hi, hh.data(), nb) || !up(&pl->d_dirs_lo, hl.data(), nb))
       return dev_fail(KSUM_ENOMEM, "device allocation");
+    if (split_tiled(*pl)) {
+      // the same values step-tiled for the GEMM fed by direct LDS copies
+      std::vector<uint16_t> ht(2 * hd.size());
+      const int nst = pl->d_pad / kGemmBK;
+      for (int s = 0; s < nst; ++s)
+        for (int64_t r = 0; r < pl->P_pad; ++r) {
+          uint16_t *dst = ht.data() + ((size_t)s * pl->P_pad + r) * 32;
+          const size_t src = (size_t)r * pl->d_pad + (size_t)s * kGemmBK;
+          for (int c = 0; c < 4; ++c) {
+            const uint16_t *from = (c < 2 ? hh.data() : hl.data()) + src + (c & 1) * 8;
+            std::copy(from, from + 8, dst + 8 * (c ^ tile_swz(r)));
+          }
+        }
+      if (!up(&pl->d_dirs_tiled, ht.data(), 2 * nb)) return dev_fail(KSUM_ENOMEM, "device allocation");
+    }
   }
   if (pl->method == KSUM_1D_NFFT) {
     const int n = pl->n_grid, m = pl->params.window_m, os = pl->params.oversample;
@@ -519,6 +541,7 @@ static hipError_t run_pipeline(ksum_plan *plan, const Layout &lay, const void *x
   a.ldd = ldd;
   a.w = f64 ? wsp<float>(a, lay.off_wf) : static_cast<const float *>(w);
   hipError_t e = launch_weight_prep(a, f64 ? static_cast<const double *>(w) : nullptr);
+  if (e == hipSuccess && lay.presplit) e = launch_split_points(a);
   for (int32_t p0 = 0; p0 < plan->P && e == hipSuccess; p0 += lay.B) {
     a.p0 = p0;
     a.nsl = std::min(lay.B, plan->P - p0);
@@ -682,17 +705,17 @@ ksum_status ksum_execute_noalloc(ksum_plan *plan, const float *x, int64_t N, con
   // the largest slice batch (at most the plan's) whose workspace fits the scratch; the
   // result does not depend on the batch size
   const size_t cap = KSUM_NOALLOC_SCRATCH_BYTES;
-  const Layout one = make_layout(*plan, N, M, 1);
+  const Layout one = make_layout(*plan, N, M, 1, false);
   if (one.total > cap)
     return fail(KSUM_EWORKSPACE, "N + M too large for the static scratch: one slice per batch needs " +
                                      std::to_string(one.total) + " bytes, the scratch holds " + std::to_string(cap));
   int32_t lo = 1, hi = make_layout(*plan, N, M).B;
   while (lo < hi) {
     const int32_t mid = lo + (hi - lo + 1) / 2;
-    if (make_layout(*plan, N, M, mid).total <= cap) lo = mid;
+    if (make_layout(*plan, N, M, mid, false).total <= cap) lo = mid;
     else hi = mid - 1;
   }
-  const Layout lay = make_layout(*plan, N, M, lo);
+  const Layout lay = make_layout(*plan, N, M, lo, false);
   int prev = 0;
   (void)hipGetDevice(&prev);
   if (prev != plan->params.device && hipSetDevice(plan->params.device) != hipSuccess)
@@ -788,6 +811,7 @@ ksum_status ksum_backward(ksum_plan *plan, const float *x, int64_t N, const floa
     if (grad_x) e = launch_fill_zero(Dx, N * ldd, sm);
     if (e == hipSuccess) e = launch_weight_prep(ax, nullptr);
   }
+  if (e == hipSuccess && (need_y ? ly : lx).presplit) e = launch_split_points(need_y ? ay : ax);
   for (int32_t p0 = 0; p0 < plan->P && e == hipSuccess; p0 += ly.B) {
     ay.p0 = ax.p0 = p0;
     ay.nsl = ax.nsl = std::min(ly.B, plan->P - p0);
@@ -845,7 +869,7 @@ ksum_status ksum_backward(ksum_plan *plan, const float *x, int64_t N, const floa
 static const char *kStageNames[ST_COUNT] = {
     "misc", "project", "setup", "ndft_adjoint", "ndft_forward", "nfft_spread", "nfft_grid",
     "nfft_interp", "sort_hist", "sort_scan", "sort_scatter", "sort_group", "accumulate", "sort_fallback",
-    "backproject"};
+    "backproject", "split_points"};
 
 int32_t ksum_stage_count(void) { return ST_COUNT; }
 

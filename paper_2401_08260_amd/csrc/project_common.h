@@ -67,6 +67,10 @@ struct GemmCtl {
   int n_col_tiles, n_row_tiles;
   const uint16_t *dirs_hi, *dirs_lo;   // split-BF16 directions [P_pad][d_pad] (split path only)
   int z_vec4;             // Z rows are 16-byte aligned (ldz % 4 == 0): 16-byte stores
+  const uint16_t *dirs_t;  // step-tiled split directions [d_pad / 16][a_rows][32], or null
+  const uint16_t *pts_t;   // step-tiled split points [d_pad / 16][b_rows][32] in union order (zero
+                           // past L and d), or null: the points are split inside the GEMM
+  int64_t a_rows, b_rows;
 };
 
 }  // namespace ksum

@@ -28,7 +28,10 @@ MIXED_TOL = 2e-5
 
 @pytest.mark.parametrize("N,M,d,P,f64", [(300, 200, 784, 16, False), (1000, 77, 50, 130, False),
                                          (5, 3, 10, 1, False), (129, 1, 3, 2, False),
-                                         (513, 300, 33, 129, False), (700, 260, 12, 7, True)])
+                                         (513, 300, 33, 129, False), (700, 260, 12, 7, True),
+                                         # more than 8 tiles of 256 slices: points split once per call
+                                         # (step-tiled, fed to the GEMM by direct LDS copies)
+                                         (2000, 1000, 64, 2061, False), (1501, 700, 50, 2100, True)])
 def test_split_bf16_projection_bound(N, M, d, P, f64):
     note(f"split-bf16 projection N={N} M={M} d={d} P={P} f64={f64}")
     rng = np.random.default_rng(N + d)
