@@ -59,7 +59,7 @@ struct SortArgs {
   uint32_t *fail_count; // groups handed to the fallback kernel (zeroed by the scan kernel, or by the
                         // host-side launch when the buckets are reused)
   uint32_t *fail_list;  // [nsl * G] work items
-  int4 *desc;           // [nsl][G] (first bucket, first entry, end entry, 0) of each group
+  int4 *desc;           // [nsl][G] (first bucket, first entry, end entry, last bucket) of each group
   int32_t deriv;        // 0: t = the sums; 1: t = their derivatives at the targets
 };
 
@@ -195,7 +195,10 @@ __global__ __launch_bounds__(1024) void sort_scan_kernel(SortArgs a) {
         desc[g2].x = b;                  // first bucket
         desc[g2].y = (int)sboff[b];      // first entry
       }
-      if (last) desc[g2].z = (int)sboff[b + 1];   // end entry
+      if (last) {
+        desc[g2].z = (int)sboff[b + 1];   // end entry
+        desc[g2].w = b;                   // last bucket
+      }
     }
   }
   if (threadIdx.x == 0) {
@@ -691,7 +694,7 @@ __device__ void stream_pass(GroupShared &g, const unsigned long long *src, unsig
 // Locates work item (slice, group): the buckets b whose start offset lies in
 // [group * kSortHalf, (group + 1) * kSortHalf), i.e. whole consecutive buckets.
 struct GroupDesc {
-  int p, b_lo;
+  int p, b_lo, b_hi;
   int64_t e_lo;
   int n;
 };
@@ -701,6 +704,7 @@ __device__ __forceinline__ GroupDesc group_desc(const SortArgs &a, int64_t item)
   GroupDesc d;
   d.p = (int)(item / a.G);
   d.b_lo = v.x;
+  d.b_hi = v.w;
   d.e_lo = v.y;
   d.n = v.z - v.y;
   return d;
@@ -856,7 +860,6 @@ struct FastShared {
   uint32_t cnt[kNS + kNS / 4];
   double pr[2 * kFWaves];      // wave totals of the (A, S) prefix scan
   uint32_t cr[kFWaves];        // wave totals of the counter scan
-  uint32_t red[2 * kFWaves];
   uint32_t flag;
 };
 
@@ -877,9 +880,18 @@ __device__ __forceinline__ void push_fallback(const SortArgs &a, int64_t item) {
   if (threadIdx.x == 0) a.fail_list[atomicAdd(a.fail_count, 1u)] = (uint32_t)item;
 }
 
-__device__ __forceinline__ int sub_bucket(uint32_t key, float zlo, float inv) {
-  const float q = (key_float(key) - zlo) * inv;
-  return (q < (float)kNS) ? (int)q : kNS - 1;
+// Sub-bucket of a key within its group: the group's buckets [b_lo, b_hi] cut into kNS
+// equal parts of the bucket coordinate q = (z - c_min) w, the same FP32 expression
+// that put the key in its bucket (so q >= b_lo).  A monotone map of the key, so
+// sub-bucket order is value order.
+struct SubMap {
+  float fcmin, invw, qlo, scale;
+};
+
+__device__ __forceinline__ int sub_bucket(uint32_t key, const SubMap &m) {
+  const float q = (key_float(key) - m.fcmin) * m.invw;
+  const float s = (q - m.qlo) * m.scale;
+  return (s < (float)kNS) ? (int)s : kNS - 1;
 }
 
 // Per-group scalars the scan needs (bucket prefixes, slice totals, slice
@@ -888,6 +900,7 @@ struct GroupScalars {
   long long preA, preS, totA, totS;
   double cmid;
   int eS;
+  SubMap sub;
 };
 
 __device__ __forceinline__ GroupScalars group_scalars(const SortArgs &a, const GroupDesc &d) {
@@ -899,6 +912,10 @@ __device__ __forceinline__ GroupScalars group_scalars(const SortArgs &a, const G
   s.totS = a.tot[2 * d.p + 1];
   s.cmid = a.params[d.p].cmid;
   s.eS = a.params[d.p].eS;
+  s.sub.fcmin = a.params[d.p].fcmin;
+  s.sub.invw = a.params[d.p].inv_width;
+  s.sub.qlo = (float)d.b_lo;
+  s.sub.scale = (float)kNS / (float)(d.b_hi - d.b_lo + 1);
   return s;
 }
 
@@ -977,7 +994,11 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
   }
   if (item + gx < hi) nd2 = group_desc(a, item + gx);
   const int eA = (int)a.misc[1];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // the first group's counters are cleared here, every later group's at the end of the
+  // group before it (the flag likewise)
+  for (int i = threadIdx.x; i < kNS + kNS / 4; i += kFThreads) f.cnt[i] = 0;
+  if (threadIdx.x == 0) f.flag = 0;
+  __syncthreads();
   while (item < hi) {
     const GroupDesc d = nd;
     unsigned long long kc[kFPer];
@@ -1005,43 +1026,10 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
       const uint32_t idx = (uint32_t)(kc[q] >> 32);
       wv[q] = (threadIdx.x + kFThreads * q < n && (int64_t)idx >= a.M) ? a.w[idx - a.M] : 0.f;
     }
-    // key range of the group (padding keys are ~0 in the low word: excluded from the max)
-    uint32_t kmin = 0xffffffffu, kmax = 0u;
-#pragma unroll
-    for (int q = 0; q < kFPer; ++q) {
-      if (threadIdx.x + kFThreads * q < n) {
-        kmin = min(kmin, (uint32_t)kc[q]);
-        kmax = max(kmax, (uint32_t)kc[q]);
-      }
-    }
-    kmin = wave_min_u32(kmin);
-    kmax = wave_max_u32(kmax);
-    if (lane == 0) {
-      f.red[wid] = kmin;
-      f.red[kFWaves + wid] = kmax;
-    }
-    for (int i = threadIdx.x; i < kNS + kNS / 4; i += kFThreads) f.cnt[i] = 0;
-    if (threadIdx.x == 0) f.flag = 0;
-    __syncthreads();
-    kmin = f.red[0];
-    kmax = f.red[kFWaves];
-#pragma unroll
-    for (int w2 = 1; w2 < kFWaves; ++w2) {
-      kmin = min(kmin, f.red[w2]);
-      kmax = max(kmax, f.red[kFWaves + w2]);
-    }
-    const float zlo = key_float(kmin), zhi = key_float(kmax);
-    const double inv_d = (double)kNS / ((double)zhi - (double)zlo);
-    if (kmin == kmax || !(inv_d < 1e30)) {
-      __syncthreads();
-      push_fallback(a, cur_item);
-      continue;
-    }
-    const float inv = (float)inv_d;
     int sb[kFPer];
 #pragma unroll
     for (int q = 0; q < kFPer; ++q) {
-      sb[q] = sub_bucket((uint32_t)kc[q], zlo, inv);
+      sb[q] = sub_bucket((uint32_t)kc[q], gs.sub);
       if (threadIdx.x + kFThreads * q < n) atomicAdd(&f.cnt[pad4(sb[q])], 1u);
     }
     __syncthreads();
@@ -1082,7 +1070,7 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
       const int i = threadIdx.x + kFThreads * q;
       if (i < n) {
         const uint32_t kk = f.K[pad8(i)], ii = f.I[pad8(i)];
-        const int s = sub_bucket(kk, zlo, inv);
+        const int s = sub_bucket(kk, gs.sub);
         const int e = (int)f.cnt[pad4(s)];
         const int b = s ? (int)f.cnt[pad4(s - 1)] : 0;
         int rank = 0;
@@ -1097,13 +1085,16 @@ __global__ __launch_bounds__(kFThreads, 4) void sort_fast_kernel(SortArgs a) {
       }
     }
     __syncthreads();
-    if (f.flag) {
-      __syncthreads();
+    // a run too long to rank (equal or tightly clustered keys) hands the group over
+    const bool handed_over = f.flag != 0;
+    // the counters are not read again in this group: clear them for the next one
+    for (int i = threadIdx.x; i < kNS + kNS / 4; i += kFThreads) f.cnt[i] = 0;
+    if (handed_over)
       push_fallback(a, cur_item);
-      continue;
-    }
-    scan_emit_fast<DERIV>(a, p, gs, eA, f, n, d.e_lo);
+    else
+      scan_emit_fast<DERIV>(a, p, gs, eA, f, n, d.e_lo);
     __syncthreads();
+    if (threadIdx.x == 0) f.flag = 0;
   }
 }
 

@@ -18,10 +18,12 @@ CASES = [
     ("negdist", dict(), 64, 2100, 3001, 2003),
     ("laplacian", dict(sigma=2.0, n_coeff=128, T=0.125), 50, 2311, 2500, 1700),
     ("gaussian", dict(sigma=1.5, n_coeff=128, T=0.02, method="nfft"), 17, 2053, 4099, 777),
+    # batches of 1000 slices: slice tiles start at rows that are not multiples of 32
+    ("negdist", dict(slice_batch=1000), 96, 2600, 1800, 1300),
 ]
 
 
-@pytest.mark.parametrize("kernel,params,d,P,N,M", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("kernel,params,d,P,N,M", CASES, ids=[f"{c[0]}-P{c[3]}" for c in CASES])
 def test_presplit_matches_split_in_gemm(kernel, params, d, P, N, M):
     import torch
     import paper_2401_08260_amd as ks
