@@ -39,6 +39,7 @@ struct SetupArgs {
 };
 
 constexpr int kSeriesTab = 512;   // tabulated term ratios; longer series divide per term
+constexpr int kFftHalf = 2048;    // sample counts L up to 2 kFftHalf (powers of two) take the FFT
 
 // Term ratios of the counterpart series, one table per chain (computed once per block):
 //  Laplacian (Table "tab:kernels"), a = alpha t: the even and odd chains of
@@ -178,8 +179,12 @@ __global__ __launch_bounds__(256) void slice_setup_kernel(SetupArgs a) {
   }
   // Tapered-coefficient recipe (Laplacian smooth part, Matern): samples v_j of the
   // function times the taper on u_j = -1/2 + j/L, then c_k = (1/L) sum_j v_j cos(2 pi k u_j).
+  // The samples depend on |u_j| only, so v_{L-j} = v_j: half of them are evaluated.
   __shared__ SeriesTab tab;
-  __shared__ double part[2048];
+  __shared__ union {
+    double part[2048];
+    double2 z[2][kFftHalf];
+  } sh;
   const bool lap = (a.kernel == KSUM_LAPLACIAN);
   for (int i = threadIdx.x; i < kSeriesTab; i += blockDim.x) {
     tab.r0[i] = lap ? lap_r0(2 * i, a.d) : mat_r0(i, a.d);
@@ -187,22 +192,68 @@ __global__ __launch_bounds__(256) void slice_setup_kernel(SetupArgs a) {
   }
   __syncthreads();
   const int L = a.lap_L;
-  double *v = a.lapv + (int64_t)p * L;
+  const int K1 = a.K + 1;
+  const bool use_fft = (L & (L - 1)) == 0 && L >= 64 && L <= 2 * kFftHalf && K1 <= L / 2;
+  // samples go to LDS for the FFT (as the complex sequence v_{2m} + i v_{2m+1}), else to
+  // the workspace
+  double *v = use_fft ? reinterpret_cast<double *>(sh.z[0]) : a.lapv + (int64_t)p * L;
   const double inv_scale = 1.0 / (a.sigma * sp.tau);   // alpha / tau, or 1 / (beta tau)
-  for (int j = threadIdx.x; j < L; j += blockDim.x) {
+  for (int j = threadIdx.x; j <= L / 2; j += blockDim.x) {
     const double u = -0.5 + (double)j / (double)L;
     const double au = fabs(u);
     const double taper = 0.5 * erfc((au - 0.375) * 37.0);
     const double f = lap ? laplace_k1_series(inv_scale * au, a.d, a.cd, tab)
                          : matern32_series(inv_scale * au, a.d, a.matern_c3, tab);
     v[j] = f * taper;
+    if (j > 0 && j < L - j) v[L - j] = f * taper;
   }
   __syncthreads();
-  // DFT: c_k = (1/L) sum_j v_j cos(2 pi k u_j) = (-1)^k (1/L) sum_j v_j cos(2 pi k j / L), the
-  // cosine by rotation from the exact table value every 64 steps.  The j range of each k
-  // is split over S threads (up to 8, K1 S <= 2048), so that every thread runs short,
-  // independent rotation chains; the partial sums are added in order.
-  const int K1 = a.K + 1;
+  auto finish = [&](int k, double acc) {
+    double c = acc / (double)L;
+    if (k & 1) c = -c;
+    if (fabs(c) <= a.eps) c = 0.0;
+    if (a.nfft) c *= (double)a.deconv[k];
+    coef[k] = (float)c;
+  };
+  if (use_fft) {
+    // sum_j v_j cos(2 pi k j / L) = Re V_k, V the length-L DFT of the real v: a length-N
+    // complex FFT (N = L / 2, radix-2 Stockham in LDS, twiddles from the exact cosine
+    // table) of z_m = v_{2m} + i v_{2m+1}, then V_k = E_k + e^{-2 pi i k / L} O_k with
+    // E_k = (Z_k + conj Z_{N-k}) / 2 and O_k = (Z_k - conj Z_{N-k}) / (2 i).
+    const int N = L / 2, qL = L / 4;
+    double2 *x = sh.z[0], *y = sh.z[1];
+    for (int Ls = 1; Ls < N; Ls <<= 1) {
+      const int tstep = N / (2 * Ls);
+      for (int j = threadIdx.x; j < N / 2; j += blockDim.x) {
+        const int k = j & (Ls - 1);
+        const int ang = 2 * k * tstep;                   // e^{-2 pi i k tstep / N}, in 1/L turns
+        const double wc = a.costab[ang], ws = a.costab[(ang - qL + L) % L];
+        const double2 A = x[j], B = x[j + N / 2];
+        const double2 b = make_double2(B.x * wc + B.y * ws, B.y * wc - B.x * ws);
+        const int o = 2 * j - k;
+        y[o] = make_double2(A.x + b.x, A.y + b.y);
+        y[o + Ls] = make_double2(A.x - b.x, A.y - b.y);
+      }
+      __syncthreads();
+      double2 *tmp = x;
+      x = y;
+      y = tmp;
+    }
+    for (int k = threadIdx.x; k < K1; k += blockDim.x) {
+      const double2 Zk = x[k], Zn = x[(N - k) % N];
+      const double ex = 0.5 * (Zk.x + Zn.x);             // Re E_k
+      const double ox = 0.5 * (Zk.y + Zn.y);             // Re O_k
+      const double oy = -0.5 * (Zk.x - Zn.x);            // Im O_k
+      const double c = a.costab[k], s = a.costab[(k - qL + L) % L];
+      finish(k, ex + c * ox + s * oy);                   // Re (E_k + (cos - i sin) O_k)
+    }
+    return;
+  }
+  // Other sample counts, a direct DFT: c_k = (1/L) sum_j v_j cos(2 pi k u_j) =
+  // (-1)^k (1/L) sum_j v_j cos(2 pi k j / L), the cosine by rotation from the exact table
+  // value every 64 steps.  The j range of each k is split over S threads (up to 8,
+  // K1 S <= 2048), so that every thread runs short, independent rotation chains; the
+  // partial sums are added in order.
   const int qL = L / 4;                    // sin(x) = cos(x - pi/2)
   auto dft_range = [&](int k, int j0, int j1) {
     const int kst = k % L;
@@ -221,13 +272,6 @@ __global__ __launch_bounds__(256) void slice_setup_kernel(SetupArgs a) {
     }
     return acc;
   };
-  auto finish = [&](int k, double acc) {
-    double c = acc / (double)L;
-    if (k & 1) c = -c;
-    if (fabs(c) <= a.eps) c = 0.0;
-    if (a.nfft) c *= (double)a.deconv[k];
-    coef[k] = (float)c;
-  };
   const int S = max(1, min(8, 2048 / K1));
   if (S == 1) {
     for (int k = threadIdx.x; k < K1; k += blockDim.x) finish(k, dft_range(k, 0, L));
@@ -237,12 +281,12 @@ __global__ __launch_bounds__(256) void slice_setup_kernel(SetupArgs a) {
   for (int it = threadIdx.x; it < K1 * S; it += blockDim.x) {
     const int k = it % K1, sidx = it / K1;
     const int j0 = min(L, sidx * span), j1 = min(L, j0 + span);
-    part[it] = dft_range(k, j0, j1);
+    sh.part[it] = dft_range(k, j0, j1);
   }
   __syncthreads();
   for (int k = threadIdx.x; k < K1; k += blockDim.x) {
     double acc = 0.0;
-    for (int sidx = 0; sidx < S; ++sidx) acc += part[sidx * K1 + k];
+    for (int sidx = 0; sidx < S; ++sidx) acc += sh.part[sidx * K1 + k];
     finish(k, acc);
   }
 }
