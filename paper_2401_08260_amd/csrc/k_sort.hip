@@ -922,20 +922,22 @@ __device__ __forceinline__ GroupScalars group_scalars(const SortArgs &a, const G
 // Scan of a sorted group: FP64 prefix sums inside the group, taken in its
 // canonical (key, index) order (so the rounding is the same on every run), on
 // top of the exact fixed-point prefix of the group's first bucket.  W holds the
-// weights of the sources (0 for targets).  Thread t owns sorted positions
-// [8t, 8t+8); the entries are read from LDS again for the output pass rather
-// than kept in registers.  In derivative mode a target also adds the sources
+// weights of the sources (0 for targets).  Thread t owns the sorted positions
+// [per t, per (t + 1)) with per = ceil(n / threads), so that every wave takes part
+// however large the group; the entries are read from LDS again for the output pass
+// rather than kept in registers.  In derivative mode a target also adds the sources
 // tied with it: the rest of its run of equal keys (targets precede tied sources
 // in the (key, index) order, and a run never crosses a bucket).
 template <bool DERIV>
 __device__ __forceinline__ void scan_emit_fast(const SortArgs &a, int p, const GroupScalars &gs, int eA,
                                                FastShared &f, int n, int64_t out_pos) {
-  const int i0 = threadIdx.x * kFPer;
+  const int per = (n + kFThreads - 1) / kFThreads;   // <= kFPer
+  const int i0 = threadIdx.x * per;
   double lA = 0.0, lS = 0.0;
 #pragma unroll
   for (int q = 0; q < kFPer; ++q) {
     const int j = i0 + q;
-    if (j < n) {
+    if (q < per && j < n) {
       const int e = pad8(f.inv[pad8(j)]);
       const double v = (double)f.W[e];
       lA += v;
@@ -951,7 +953,7 @@ __device__ __forceinline__ void scan_emit_fast(const SortArgs &a, int p, const G
 #pragma unroll
   for (int q = 0; q < kFPer; ++q) {
     const int j = i0 + q;
-    if (j < n) {
+    if (q < per && j < n) {
       const int e = pad8(f.inv[pad8(j)]);
       const uint32_t kk = f.K[e], ii = f.I[e];
       const double v = (double)f.W[e];
