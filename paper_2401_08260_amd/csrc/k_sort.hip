@@ -924,8 +924,8 @@ __device__ __forceinline__ GroupScalars group_scalars(const SortArgs &a, const G
 // top of the exact fixed-point prefix of the group's first bucket.  W holds the
 // weights of the sources (0 for targets).  Thread t owns the sorted positions
 // [per t, per (t + 1)) with per = ceil(n / threads), so that every wave takes part
-// however large the group; the entries are read from LDS again for the output pass
-// rather than kept in registers.  In derivative mode a target also adds the sources
+// however large the group; its entries stay in registers from the prefix pass to the
+// output pass.  In derivative mode a target also adds the sources
 // tied with it: the rest of its run of equal keys (targets precede tied sources
 // in the (key, index) order, and a run never crosses a bucket).
 template <bool DERIV>
@@ -934,14 +934,22 @@ __device__ __forceinline__ void scan_emit_fast(const SortArgs &a, int p, const G
   const int per = (n + kFThreads - 1) / kFThreads;   // <= kFPer
   const int i0 = threadIdx.x * per;
   double lA = 0.0, lS = 0.0;
+  uint32_t kq[kFPer], iq[kFPer];
+  float wq[kFPer];
 #pragma unroll
   for (int q = 0; q < kFPer; ++q) {
     const int j = i0 + q;
+    kq[q] = 0;
+    iq[q] = 0;
+    wq[q] = 0.f;
     if (q < per && j < n) {
       const int e = pad8(f.inv[pad8(j)]);
-      const double v = (double)f.W[e];
+      kq[q] = f.K[e];
+      iq[q] = f.I[e];
+      wq[q] = f.W[e];
+      const double v = (double)wq[q];
       lA += v;
-      lS += v * ((double)key_float(f.K[e]) - gs.cmid);
+      lS += v * ((double)key_float(kq[q]) - gs.cmid);
     }
   }
   double gA, gS;
@@ -954,9 +962,8 @@ __device__ __forceinline__ void scan_emit_fast(const SortArgs &a, int p, const G
   for (int q = 0; q < kFPer; ++q) {
     const int j = i0 + q;
     if (q < per && j < n) {
-      const int e = pad8(f.inv[pad8(j)]);
-      const uint32_t kk = f.K[e], ii = f.I[e];
-      const double v = (double)f.W[e];
+      const uint32_t kk = kq[q], ii = iq[q];
+      const double v = (double)wq[q];
       const double zb = (double)key_float(kk) - gs.cmid;
       if ((int64_t)ii < a.M) {
         if (DERIV) {
