@@ -316,6 +316,24 @@ def test_laplace_workload_reduced():
     assert_parity(r["s"], ref)
 
 
+@pytest.mark.parametrize("n_coeff", [128, 512])
+def test_laplace_coefficient_transforms(n_coeff):
+    """The Laplacian's smooth-part coefficients come from 16 n_coeff samples: up to 4096 of
+    them (128 coefficients: 2048 samples) the set-up takes an FFT, beyond that (512: 8192)
+    its direct transform.  Both against the oracle's own quadrature."""
+    rng = np.random.default_rng(96 + n_coeff)
+    N, M, d, P = 2500, 1800, 24, 5
+    x = rng.random((N, d), dtype=np.float32)
+    y = rng.random((M, d), dtype=np.float32)
+    w = rng.random(N).astype(np.float32)
+    sigma = float(np.sqrt(d / 6.0))
+    note(f"laplace coefficients n_coeff={n_coeff}")
+    r = run_gpu("laplacian", x, y, w, P, seed=9, sigma=sigma, n_coeff=n_coeff, T=0.125, probe=True)
+    ref, ts = oracle_s("laplacian", x, y, w, r["xi"], sigma, "nfft", n_coeff, 0.125, slices=True)
+    assert_parity(r["s"], ref)
+    assert_parity(r["t"], ts, what="t")
+
+
 def test_negdist_workload_full_size():
     """The negative-distance workload at its full size (N=M=1e5, d=784, P=256)."""
     wl = wlm.WORKLOADS["negdist"]
