@@ -183,7 +183,11 @@ ksum_status ksum_workspace_bytes(int32_t d, int32_t P, ksum_kernel kernel, const
 ksum_status ksum_plan_create(int32_t d, int32_t P, ksum_kernel kernel, const ksum_params *params,
                              ksum_plan **out);
 
-/* Release a plan (NULL is accepted).  Synchronises the plan's device. */
+/* Release a plan (NULL is accepted).  Its tables are freed in the order of the
+ * library's own stream after the plan's work on every stream it ran on (the host
+ * does not wait); if its work was captured into a graph, or ran on more streams
+ * than the plan tracks, the call first synchronises the plan's device.  A graph
+ * holding the plan's work must not be launched after the plan is released. */
 ksum_status ksum_plan_destroy(ksum_plan *plan);
 
 /* Copy the plan's directions (P*d FP64, row-major) to host_out. */
@@ -197,7 +201,10 @@ ksum_status ksum_workspace_size(const ksum_plan *plan, int64_t N, int64_t M, siz
  *   w   device float[N] weights             s  device float[M] output (overwritten)
  *   ws  device workspace of ws_bytes >= ksum_workspace_size(plan, N, M)
  *   stream  hipStream_t (as void*) the work is enqueued on
- * x and y may alias; s must not overlap any input or the workspace.
+ * x and y may alias; s must not overlap any input or the workspace.  Without the
+ * opt-in input check the call only enqueues kernels on the stream (no copies, no
+ * memsets, no host synchronisation), so it may be captured into a HIP graph; a
+ * launch of the graph reads and writes the buffers the capture saw.
  * EINVAL for null pointers or N, M < 1; EWORKSPACE if ws_bytes is too small. */
 ksum_status ksum_execute(ksum_plan *plan, const float *x, int64_t N, const float *y, int64_t M,
                          const float *w, float *s, void *ws, size_t ws_bytes, void *stream);

@@ -232,6 +232,13 @@ static hipError_t upload(hipStream_t ls, void **dst, const void *src, size_t byt
 // Records that the plan's work was enqueued on `stream` (after every call that launches).
 static void note_use(ksum_plan *pl, hipStream_t stream) {
   std::lock_guard<std::mutex> lock(pl->use_mu);
+  // work captured into a graph runs whenever the graph is launched, which no event
+  // recorded now can follow: the plan's release then waits for the whole device
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) {
+    pl->use_overflow = true;
+    return;
+  }
   int i = 0;
   while (i < pl->n_use && pl->use_stream[i] != stream) ++i;
   if (i == pl->n_use) {
