@@ -313,6 +313,16 @@ def test_backward_split_bf16():
     check("negdist", x, y, w, g, P, directions=xi, precision="split_bf16")
 
 
+def test_backward_split_bf16_presplit():
+    """The same with more than 8 tiles of 256 slices: the points are split once per call
+    (for the union of the gradient's first layout) and the GEMM is fed by direct LDS
+    copies; exact dyadic projections again meet the FP32 gate."""
+    note("backward split-bf16 negdist, P = 2100 (points split once per call)")
+    N, M, d, P = 1500, 1000, 64, 2100
+    x, y, w, g, xi = dyadic_case(N, M, d, P, 23, bits=16)
+    check("negdist", x, y, w, g, P, directions=xi, precision="split_bf16")
+
+
 def test_backward_matern_reduced():
     rng = np.random.default_rng(31)
     N, M, d, P = 6000, 5000, 20, 3
