@@ -347,19 +347,27 @@ def serve_replay(n_requests, rate, slots, hbm_gb, saturated=True):
         out.update(extra)
         return out
 
-    def run_served(scale, window=64):
+    def out_bytes(i):
+        r = reqs[i]
+        return 4 * (r["M"] + ((r["N"] + r["M"]) * r["d"] + r["N"] if r["grad"] else 0))
+
+    def run_served(scale, window=64, window_bytes=16 << 30):
         """Continuous batching with the split-BF16 projection; arrivals scaled by `scale`.
         scale = 0 saturates the server: requests go in as fast as it takes them, at most
-        `window` outstanding (their output buffers are allocated as they are submitted)."""
+        `window` outstanding whose output buffers (allocated as they are submitted) take
+        at most `window_bytes` together, or one if it alone is larger.  Large requests stay
+        outstanding longest, so without the byte bound the window fills with them."""
         lat, t_end_max, keep = [], 0.0, {}
         t0 = time.monotonic()
-        i = pending = 0
+        i = pending = held = 0
         while i < len(reqs) or pending:
             now = time.monotonic() - t0
-            while i < len(reqs) and reqs[i]["arrival"] * scale <= now and (scale > 0 or pending < window):
+            while i < len(reqs) and reqs[i]["arrival"] * scale <= now and (
+                    scale > 0 or pending == 0 or (pending < window and held + out_bytes(i) <= window_bytes)):
                 x, y, w, g = inputs(i)
                 s, gr = outputs(i)
                 keep[i] = (s, gr)
+                held += out_bytes(i)
                 srv.submit(i, reqs[i]["kernel"], reqs[i]["d"], reqs[i]["P"], x, y, w, s,
                            params=params(i, "split_bf16"), grad_s=g if reqs[i]["grad"] else None, grads=gr)
                 i += 1
@@ -369,7 +377,8 @@ def serve_replay(n_requests, rate, slots, hbm_gb, saturated=True):
                     raise RuntimeError(f"request {c['tag']} failed with status {c['status']}")
                 lat.append(c["t_end"] - (t0 + reqs[c["tag"]]["arrival"] * scale))
                 t_end_max = max(t_end_max, c["t_end"] - t0)
-                keep.pop(c["tag"], None)
+                if keep.pop(c["tag"], None) is not None:
+                    held -= out_bytes(c["tag"])
                 pending -= 1
             time.sleep(5e-5)
         st = srv.stats()
@@ -410,8 +419,8 @@ def serve_replay(n_requests, rate, slots, hbm_gb, saturated=True):
            "p99_speedup": base["p99_ms"] / served["p99_ms"]}
     if saturated:
         served_sat = run_served(0.0)
-        log(f"[serve] served, saturated (64 outstanding): {served_sat['value']:.3e} {UNIT} "
-            f"over {served_sat['makespan_s']:.2f} s")
+        log(f"[serve] served, saturated (<= 64 outstanding, <= 16 GiB of outputs): "
+            f"{served_sat['value']:.3e} {UNIT} over {served_sat['makespan_s']:.2f} s")
         base_sat = run_baseline(0.0)
         log(f"[serve] one at a time, back to back: {base_sat['value']:.3e} {UNIT} "
             f"over {base_sat['makespan_s']:.2f} s")
