@@ -432,6 +432,72 @@ def serve_replay(n_requests, rate, slots, hbm_gb, saturated=True):
     return out
 
 
+def graph_probe():
+    """`--graph-probe`: what a HIP graph would save a served request.  For small and
+    medium requests of each path: median latency of one call waiting for its result,
+    launched directly or replayed from a graph captured once, the same back to back,
+    and the host cost of capturing and instantiating a graph (what a request pays when
+    no earlier request had its shape and buffers)."""
+    import torch
+    import paper_2401_08260_amd as ks
+
+    dev = torch.device("cuda:0")
+    rows = []
+    cases = (("negdist", {}), ("laplacian", dict(sigma=5.0, n_coeff=256, T=0.125)),
+             ("gaussian", dict(sigma=5.0, n_coeff=128, T=0.02, method="nfft", oversample=2, window_m=6)))
+    for kernel, kw in cases:
+        for n in (1000, 10000, 100000):
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(1)
+            x = torch.rand((n, 128), device=dev, generator=gen)
+            y = torch.rand((n, 128), device=dev, generator=gen)
+            w = torch.rand(n, device=dev, generator=gen)
+            plan = ks.Plan(128, 64, kernel, seed=64, **kw)
+            s = torch.empty(n, device=dev)
+            st = torch.cuda.Stream()
+
+            def med(fn, reps=50):
+                t = []
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    fn()
+                    st.synchronize()
+                    t.append(time.perf_counter() - t0)
+                return 1e6 * float(np.median(t))
+
+            def b2b(fn, reps=100):
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    fn()
+                st.synchronize()
+                return 1e6 * (time.perf_counter() - t0) / reps
+
+            with torch.cuda.stream(st):
+                for _ in range(3):
+                    plan(x, y, w, out=s)
+                direct = lambda: plan(x, y, w, out=s)
+                r = {"kernel": kernel, "N": n, "M": n, "d": 128, "P": 64,
+                     "direct_p50_us": med(direct), "direct_b2b_us": b2b(direct)}
+                gr = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(gr, stream=st):
+                    plan(x, y, w, out=s)
+                st.synchronize()
+                r["graph_p50_us"] = med(gr.replay)
+                r["graph_b2b_us"] = b2b(gr.replay)
+                t0 = time.perf_counter()
+                for _ in range(10):
+                    g2 = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g2, stream=st):
+                        plan(x, y, w, out=s)
+                r["capture_instantiate_us"] = 1e6 * (time.perf_counter() - t0) / 10
+            log(f"[graph] {kernel:9s} N=M={n:6d}: direct {r['direct_p50_us']:.1f} us ({r['direct_b2b_us']:.1f} "
+                f"back to back), graph {r['graph_p50_us']:.1f} us ({r['graph_b2b_us']:.1f}), capture + "
+                f"instantiate {r['capture_instantiate_us']:.1f} us")
+            rows.append(r)
+            del plan
+    print(json.dumps({"graph_probe": rows}), flush=True)
+
+
 def bench_serve(args):
     """`--workload serve`: the serving replay as its own bench line."""
     r = serve_replay(args.serve_requests, args.serve_rate, args.serve_slots, args.serve_hbm_gb, saturated=True)
@@ -543,6 +609,8 @@ def main():
                     help="form of the headline (the other is timed beside it)")
     ap.add_argument("--backward", action="store_true",
                     help="also time one gradient step (grad_x, grad_y, grad_w for an upstream grad_s) at P")
+    ap.add_argument("--graph-probe", action="store_true",
+                    help="only measure what replaying a captured HIP graph saves a small request")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device (reference for the HBM traffic counters)")
     args = ap.parse_args()
@@ -556,6 +624,9 @@ def main():
     import torch
     import paper_2401_08260_amd as ks
 
+    if args.graph_probe:
+        graph_probe()
+        return
     if args.workload == "serve":
         bench_serve(args)
         return

@@ -86,7 +86,8 @@ int window_degree_for(int m);
 // Fits phi((fr + m - 1 - j)/n) / phi(0), fr in [0,1), j = 0..m-1, by polynomials
 // in x = fr - 1/2 of degree deg: Chebyshev interpolation at deg+1 Chebyshev
 // nodes of [-1/2, 1/2] (near-minimax), converted to monomials.  The fit is
-// checked on a fine grid; err receives a message if it is worse than 1e-9.
+// checked on a fine grid; err receives a message if it is worse than 1e-6 (the
+// degrees chosen reach 5e-8).
 bool build_window_poly(int m, int n, int oversample, WindowPoly *out, std::string *err) {
   (void)n;
   const int deg = window_degree_for(m);

@@ -534,11 +534,11 @@ hipError_t launch_nfft(const ExecArgs &a) {
   switch (a.plan->params.window_m) {
     case 2: launch_nfft_m<2, 9>(f, a); break;
     case 3: launch_nfft_m<3, 9>(f, a); break;
-    case 4: launch_nfft_m<4, 9>(f, a); break;
-    case 5: launch_nfft_m<5, 9>(f, a); break;
-    case 6: launch_nfft_m<6, 8>(f, a); break;
-    case 7: launch_nfft_m<7, 8>(f, a); break;
-    case 8: launch_nfft_m<8, 8>(f, a); break;
+    case 4: launch_nfft_m<4, 7>(f, a); break;
+    case 5: launch_nfft_m<5, 7>(f, a); break;
+    case 6: launch_nfft_m<6, 7>(f, a); break;
+    case 7: launch_nfft_m<7, 7>(f, a); break;
+    case 8: launch_nfft_m<8, 7>(f, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -574,18 +574,19 @@ hipError_t launch_nfft_interp(const ExecArgs &a, float *s, bool first, bool last
   switch (pl.params.window_m) {
     case 2: launch_interp_m<2, 9>(f, c, a); break;
     case 3: launch_interp_m<3, 9>(f, c, a); break;
-    case 4: launch_interp_m<4, 9>(f, c, a); break;
-    case 5: launch_interp_m<5, 9>(f, c, a); break;
-    case 6: launch_interp_m<6, 8>(f, c, a); break;
-    case 7: launch_interp_m<7, 8>(f, c, a); break;
-    case 8: launch_interp_m<8, 8>(f, c, a); break;
+    case 4: launch_interp_m<4, 7>(f, c, a); break;
+    case 5: launch_interp_m<5, 7>(f, c, a); break;
+    case 6: launch_interp_m<6, 7>(f, c, a); break;
+    case 7: launch_interp_m<7, 7>(f, c, a); break;
+    case 8: launch_interp_m<8, 7>(f, c, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 // Degree of the per-tap window polynomials: the smallest that fits the Kaiser-Bessel
-// taps to about 1e-8 of phi(0) for oversampling 2..8 (narrow windows are steeper per cell).
-int window_degree_for(int m) { return m <= 5 ? 9 : 8; }
+// taps to within 5e-8 of phi(0) for oversampling 2..8 (narrow windows are steeper per
+// cell).  With FP32 coefficients no degree gets below about 2e-8.
+int window_degree_for(int m) { return m <= 3 ? 9 : 7; }
 
 }  // namespace ksum
