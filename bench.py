@@ -732,10 +732,12 @@ def main():
                     "P": wl.P, "ms_per_step": ms_b, "stage_ms_per_step": {k: v[0] for k, v in st_b.items()}}
         if "backproject" in st_b:
             bms, bl = st_b["backproject"]
+            # the work is per launch (the mean of the grad_y and grad_x launches): rate per launch
             b_bound, b_amt, b_unit, b_pk = kernel_work("backproject", wl, wl.P)
-            backward["backproject_roofline"] = {"bound": b_bound, "avg_launch_ms": bms / bl,
-                                                "achieved": b_amt / (bms * 1e-3), "peak": b_pk, "unit": b_unit,
-                                                "frac": b_amt / (bms * 1e-3) / b_pk}
+            b_rate = b_amt / (bms / bl * 1e-3)
+            backward["backproject_roofline"] = {"bound": b_bound, "avg_launch_ms": bms / bl, "launches": bl,
+                                                "achieved": b_rate, "peak": b_pk, "unit": b_unit,
+                                                "frac": b_rate / b_pk}
         log(f"[bench] backward (grad_x, grad_y, grad_w) at P={wl.P}: {ms_b:.3f} ms/step")
         del plan
 
