@@ -210,18 +210,22 @@ __global__ __launch_bounds__(1024) void sort_scan_kernel(SortArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// S3: scatter (key, union index) into buckets.  Each tile of kScatTile entries is
+// S3: scatter (key, union index) into buckets.  Each tile of TILE entries is
 // first ordered by bucket in LDS, so the global writes come as runs of
 // consecutive positions per bucket instead of isolated 8-byte stores.  The next
 // tile's projections are loaded while the current one is processed, the keys
 // stay in registers until they are placed, and the tile counters alternate
 // between two arrays, so a tile takes four barriers plus the one of its scan.
+// Tiles of 12288 entries (152 KB of LDS) give longer runs than tiles of 8192;
+// the launch takes whichever cuts a chunk into fewer tiles, the smaller on a tie
+// (a nearly empty last tile costs as many barriers as a full one).
 // ---------------------------------------------------------------------------
-constexpr int kScatTile = 8192;
 constexpr int kScatThreads = 1024;
-constexpr int kScatPer = kScatTile / kScatThreads;
 
+template <int TILE>
 __global__ __launch_bounds__(kScatThreads) void sort_scatter_kernel(SortArgs a) {
+  constexpr int kScatTile = TILE;
+  constexpr int kScatPer = kScatTile / kScatThreads;
   __shared__ unsigned long long tk[kScatTile];
   __shared__ uint16_t tb[kScatTile];
   __shared__ uint32_t cursor[2048], tcnt[2][2048], tstart[2048];
@@ -1141,7 +1145,11 @@ hipError_t launch_sort_path(const ExecArgs &a) {
     mark(a, ST_SORT_SCAN);
     sort_scan_kernel<<<a.nsl, 1024, 0, a.stream>>>(s);
     mark(a, ST_SORT_SCATTER);
-    sort_scatter_kernel<<<g1, kScatThreads, 0, a.stream>>>(s);
+    const int64_t chunk = (lay.L + kSortChunks - 1) / kSortChunks;
+    if ((chunk + 12287) / 12288 < (chunk + 8191) / 8192)
+      sort_scatter_kernel<12288><<<g1, kScatThreads, 0, a.stream>>>(s);
+    else
+      sort_scatter_kernel<8192><<<g1, kScatThreads, 0, a.stream>>>(s);
   } else {
     // the scan, which clears the fallback list, does not run: clear it here
     mark(a, ST_MISC);
