@@ -23,7 +23,8 @@ constexpr int kGemmBK = 16;         // K step of the projection GEMM (d is padde
 constexpr int kGemmBM = 128;        // slices per GEMM tile (P is padded to it)
 constexpr int kGemmBlocksPerCU = 3; // persistent projection blocks per CU
 constexpr int kMaxBatch = 1024;     // slices per batch (per-block min / max live in LDS)
-constexpr int kSortChunks = 16;     // chunks per slice in the bucket histogram / scatter
+constexpr int kSortChunkMax = 64;   // chunks per slice in the bucket histogram / scatter, at most
+constexpr int kSortChunkLen = 24576; // entries per chunk aimed at: two of the scatter's largest tiles
 constexpr int kNfftPPL = 128;       // sources per lane in an NFFT spread block
 constexpr int kSortCap = 4096;      // elements a bucket group may hold to be sorted in LDS
 constexpr int kSortHalf = kSortCap / 2;
@@ -123,6 +124,8 @@ struct Layout {
   int32_t B = 0;                 // slices per batch
   int32_t nb = 0;                // buckets per slice (sort path)
   int32_t sort_groups = 0;       // group slots per slice (sort path)
+  int32_t sort_nch = 0;          // chunks per slice of the histogram and the scatter
+  int64_t sort_chunk = 0;        // entries per chunk (the last one may hold fewer)
   int32_t ndft_chunks = 0;       // source chunks per slice (NDFT)
   int32_t nfft_chunks = 0;       // source chunks per slice (NFFT spread)
   int32_t win_lo = 0, win_cells = 0;   // NFFT cells touched: [win_lo, win_lo + win_cells)
@@ -141,8 +144,8 @@ struct Layout {
   size_t off_grid = 0;           // float[B][n_grid]
   size_t off_lapv = 0;           // double[B][lap_L] samples of the Laplacian recipe
   size_t off_wf = 0;             // float[N] weights converted from FP64 input
-  size_t off_hcnt = 0;           // uint32[B][kSortChunks][nb]
-  size_t off_hsum = 0;           // int64[B][kSortChunks][nb][2]
+  size_t off_hcnt = 0;           // uint32[B][sort_nch][nb]
+  size_t off_hsum = 0;           // int64[B][sort_nch][nb][2]
   size_t off_bpre = 0;           // int64[B][nb][2]  exclusive bucket prefix of (A, S)
   size_t off_boff = 0;           // uint32[B][nb + 1] bucket offsets
   size_t off_tot = 0;            // int64[B][2]      slice totals (A, S)

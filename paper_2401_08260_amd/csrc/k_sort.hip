@@ -61,6 +61,8 @@ struct SortArgs {
   uint32_t *fail_list;  // [nsl * G] work items
   int4 *desc;           // [nsl][G] (first bucket, first entry, end entry, last bucket) of each group
   int32_t deriv;        // 0: t = the sums; 1: t = their derivatives at the targets
+  int32_t nch;          // chunks per slice of the histogram and the scatter
+  int64_t chunk;        // entries per chunk (the last one may hold fewer)
 };
 
 __device__ __forceinline__ int bucket_of(float z, float fcmin, float invw, int nb) {
@@ -86,9 +88,9 @@ constexpr int kHistU = 8;
 __global__ __launch_bounds__(512) void sort_hist_kernel(SortArgs a) {
   __shared__ uint32_t cnt[2048];
   __shared__ unsigned long long sA[2048], sS[2048];
-  const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * kSortChunks);
+  const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * a.nch);
   if (work < 0) return;
-  const int p = (int)(work / kSortChunks), c = (int)(work % kSortChunks);
+  const int p = (int)(work / a.nch), c = (int)(work % a.nch);
   for (int b = threadIdx.x; b < a.nb; b += blockDim.x) {
     cnt[b] = 0;
     sA[b] = 0;
@@ -97,8 +99,7 @@ __global__ __launch_bounds__(512) void sort_hist_kernel(SortArgs a) {
   __syncthreads();
   const SliceParams sp = a.params[p];
   const int eA = (int)a.misc[1];
-  const int64_t chunk = (a.L + kSortChunks - 1) / kSortChunks;
-  const int64_t l0 = c * chunk, l1 = min(a.L, l0 + chunk);
+  const int64_t l0 = c * a.chunk, l1 = min(a.L, l0 + a.chunk);
   const float *Zp = a.Z + (int64_t)p * a.L;
   for (int64_t lb = l0; lb < l1; lb += 512 * kHistU) {
     float z[kHistU], v[kHistU];
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(512) void sort_hist_kernel(SortArgs a) {
     }
   }
   __syncthreads();
-  const int64_t base = ((int64_t)p * kSortChunks + c) * a.nb;
+  const int64_t base = ((int64_t)p * a.nch + c) * a.nb;
   for (int b = threadIdx.x; b < a.nb; b += blockDim.x) {
     a.hcnt[base + b] = cnt[b];
     a.hsum[2 * (base + b)] = (long long)sA[b];
@@ -138,11 +139,11 @@ __global__ __launch_bounds__(1024) void sort_scan_kernel(SortArgs a) {
   const int p = blockIdx.x;
   const int per = (a.nb + 1023) / 1024;   // buckets per thread (nb <= 2048)
   long long cntv[2] = {0, 0}, Av[2] = {0, 0}, Sv[2] = {0, 0};
-  const int64_t base = (int64_t)p * kSortChunks * a.nb;
+  const int64_t base = (int64_t)p * a.nch * a.nb;
   for (int q = 0; q < per; ++q) {
     const int b = threadIdx.x * per + q;
     if (b < a.nb) {
-      for (int c = 0; c < kSortChunks; ++c) {
+      for (int c = 0; c < a.nch; ++c) {
         const int64_t o = base + (int64_t)c * a.nb + b;
         cntv[q] += a.hcnt[o];
         Av[q] += a.hsum[2 * o];
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(1024) void sort_scan_kernel(SortArgs a) {
       bpre[2 * b] = eAx;
       bpre[2 * b + 1] = eSx;
       uint32_t run = (uint32_t)ec;
-      for (int c = 0; c < kSortChunks; ++c) {
+      for (int c = 0; c < a.nch; ++c) {
         const int64_t o = base + (int64_t)c * a.nb + b;
         const uint32_t v = a.hcnt[o];
         a.hcnt[o] = run;
@@ -230,18 +231,17 @@ __global__ __launch_bounds__(kScatThreads) void sort_scatter_kernel(SortArgs a) 
   __shared__ uint16_t tb[kScatTile];
   __shared__ uint32_t cursor[2048], tcnt[2][2048], tstart[2048];
   __shared__ uint32_t red[kScatThreads / 64];
-  const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * kSortChunks);
+  const int64_t work = xcd_remap(blockIdx.x, (int64_t)a.nsl * a.nch);
   if (work < 0) return;
-  const int p = (int)(work / kSortChunks), c = (int)(work % kSortChunks);
-  const int64_t base = ((int64_t)p * kSortChunks + c) * a.nb;
+  const int p = (int)(work / a.nch), c = (int)(work % a.nch);
+  const int64_t base = ((int64_t)p * a.nch + c) * a.nb;
   for (int b = threadIdx.x; b < a.nb; b += blockDim.x) {
     cursor[b] = a.hcnt[base + b];
     tcnt[0][b] = 0;
     tcnt[1][b] = 0;
   }
   const SliceParams sp = a.params[p];
-  const int64_t chunk = (a.L + kSortChunks - 1) / kSortChunks;
-  const int64_t l0 = c * chunk, l1 = min(a.L, l0 + chunk);
+  const int64_t l0 = c * a.chunk, l1 = min(a.L, l0 + a.chunk);
   const float *Zp = a.Z + (int64_t)p * a.L;
   unsigned long long *kp = a.keys + (int64_t)p * a.L;
   const int per = (a.nb + kScatThreads - 1) / kScatThreads;    // buckets per thread in the scan
@@ -1138,14 +1138,16 @@ hipError_t launch_sort_path(const ExecArgs &a) {
   s.perm = a.perm_out ? a.perm_out + (int64_t)a.p0 * lay.L : nullptr;
   s.cneg = pl.sort_const;
   s.deriv = a.deriv ? 1 : 0;
-  const unsigned g1 = (unsigned)xcd_grid((int64_t)a.nsl * kSortChunks);
+  s.nch = lay.sort_nch;
+  s.chunk = lay.sort_chunk;
+  const unsigned g1 = (unsigned)xcd_grid((int64_t)a.nsl * lay.sort_nch);
   if (!a.reuse_front) {   // histogram, scan and scatter do not depend on the derivative mode
     mark(a, ST_SORT_HIST);
     sort_hist_kernel<<<g1, 512, 0, a.stream>>>(s);
     mark(a, ST_SORT_SCAN);
     sort_scan_kernel<<<a.nsl, 1024, 0, a.stream>>>(s);
     mark(a, ST_SORT_SCATTER);
-    const int64_t chunk = (lay.L + kSortChunks - 1) / kSortChunks;
+    const int64_t chunk = lay.sort_chunk;
     if ((chunk + 12287) / 12288 < (chunk + 8191) / 8192)
       sort_scatter_kernel<12288><<<g1, kScatThreads, 0, a.stream>>>(s);
     else

@@ -161,8 +161,11 @@ Layout make_layout(const ksum_plan &pl, int64_t N, int64_t M, int32_t batch, boo
     const int64_t L = y.L;
     y.nb = (int32_t)std::min<int64_t>(2048, std::max<int64_t>(64, next_pow2((L + 511) / 512)));
     y.sort_groups = (int32_t)((L + kSortHalf - 1) / kSortHalf + 1);
-    y.off_hcnt = take((size_t)B * kSortChunks * y.nb * sizeof(uint32_t));
-    y.off_hsum = take((size_t)B * kSortChunks * y.nb * 2 * sizeof(long long));
+    // chunks of about two of the scatter's largest tiles, so that its tiles are full
+    y.sort_nch = (int32_t)std::min<int64_t>(kSortChunkMax, std::max<int64_t>(1, (L + kSortChunkLen - 1) / kSortChunkLen));
+    y.sort_chunk = (L + y.sort_nch - 1) / y.sort_nch;
+    y.off_hcnt = take((size_t)B * y.sort_nch * y.nb * sizeof(uint32_t));
+    y.off_hsum = take((size_t)B * y.sort_nch * y.nb * 2 * sizeof(long long));
     y.off_bpre = take((size_t)B * y.nb * 2 * sizeof(long long));
     y.off_boff = take((size_t)B * (y.nb + 1) * sizeof(uint32_t));
     y.off_tot = take((size_t)B * 2 * sizeof(long long));
